@@ -1,0 +1,205 @@
+"""CPU oracle for the photon transport -- TEST INFRASTRUCTURE ONLY.
+
+A plain FP64 C++ implementation (``xeoracle.cpp``) of what the HIP path
+computes, loaded with ctypes.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the library itself never
+does.  It shares no code with the HIP path: both receive the same input arrays
+built by ``paper_2203_14354_amd.workloads`` and compute independently.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xeoracle.cpp")
+_LIB = os.path.join(_HERE, "libxeoracle.so")
+
+F_DETECT, F_SENSOR_ABSORB, F_SURFACE_ABSORB, F_BULK_ABSORB = 1, 2, 3, 4
+F_ESCAPED, F_MAX_STEPS, F_NAN_ABORT, F_GEOMETRY_ERROR = 5, 6, 7, 0x100
+
+RECORD_DTYPE = np.dtype([
+    ("flag", np.int32), ("last_tri", np.int32), ("sensor", np.int32), ("steps", np.int32),
+    ("event", np.int32), ("medium", np.int32), ("n_scatter", np.int32), ("pad", np.int32),
+    ("pos", np.float64, 3), ("dir", np.float64, 3), ("pol", np.float64, 3),
+    ("time", np.float64), ("path_len", np.float64), ("sum_inv_r", np.float64),
+    ("sum_inv_t", np.float64),
+])
+assert RECORD_DTYPE.itemsize == 32 + 9 * 8 + 4 * 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (g++, OpenMP, no FMA contraction, portable -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                               ctypes.c_double)
+        L.oracle_scene_create.restype = P
+        L.oracle_scene_create.argtypes = [P, I64, P, I64, P, P, P, P, P, I32, P, P, I32, P, I32,
+                                          I32, I32]
+        L.oracle_scene_destroy.argtypes = [P]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_run.argtypes = [P, I32, I32, I64, I64, P, P, I64, I32, P, P, D, D, D, U64, U64,
+                                 I32, D, I32, I64, I64, P, P, P, I32]
+        L.oracle_philox.argtypes = [P, P, P]
+        L.oracle_u01.restype = D
+        L.oracle_u01.argtypes = [ctypes.c_uint32]
+        L.oracle_sample.argtypes = [I32, U64, U64, I64, P, P, D, D, D, P, P]
+        L.oracle_boundary.restype = I32
+        L.oracle_boundary.argtypes = [I32, P, P, P, D, D, D, P, P]
+        L.oracle_closest_hit.argtypes = [P, I64, P, P, D, D, P, I32, P, P]
+        L.oracle_max_threads.restype = I32
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Scene:
+    """Oracle copy of a mesh plus its optical tables."""
+
+    def __init__(self, mesh, channel_of_sensor=None, n_channels=None, use_bvh=False):
+        from paper_2203_14354_amd.workloads import materials_array, surfaces_array
+        self.mesh = mesh
+        self._keep = []
+
+        def keep(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        v = keep(mesh.vertices, np.float32)
+        t = keep(mesh.triangles, np.int32)
+        mi, mo = keep(mesh.mat_inner, np.int32), keep(mesh.mat_outer, np.int32)
+        su, se = keep(mesh.surface, np.int32), keep(mesh.sensor, np.int32)
+        mats = keep(materials_array(mesh.materials), np.float32)
+        sp, stags = surfaces_array(mesh.surfaces)
+        sp, stags = keep(sp, np.float32), keep(stags, np.int32)
+        if channel_of_sensor is None:
+            ch = keep(np.arange(mesh.n_sensors, dtype=np.int32), np.int32)
+            nch = mesh.n_sensors
+        else:
+            ch = keep(channel_of_sensor, np.int32)
+            nch = int(n_channels if n_channels is not None else ch.max() + 1)
+        self.n_channels = nch
+        self.handle = lib().oracle_scene_create(
+            _p(v), len(v), _p(t), len(t), _p(mi), _p(mo), _p(su), _p(se), _p(mats), len(mats),
+            _p(sp), _p(stags), len(sp), _p(ch), mesh.n_sensors, nch, 1 if use_bvh else 0)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.oracle_scene_destroy(self.handle)
+            self.handle = None
+
+    def closest_hit(self, orig, dirs, tmin=0.0, tmax=np.inf, skip=None, brute=False):
+        o = np.ascontiguousarray(orig, dtype=np.float64).reshape(-1, 3)
+        d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
+        tri = np.empty(len(o), dtype=np.int32)
+        t = np.empty(len(o), dtype=np.float64)
+        lib().oracle_closest_hit(self.handle, len(o), _p(o), _p(d), float(tmin), float(tmax),
+                                 _p(sk), 1 if brute else 0, _p(tri), _p(t))
+        return tri, t
+
+
+def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, grad_material=0,
+        i_begin=0, i_end=None, records=True, hit_map=True, grad=False, n_threads=0):
+    """Propagate launch-local photons [i_begin, i_end).  Returns a dict with
+    'records' (RECORD_DTYPE array), 'hit_map' (int64 [events, channels]) and
+    'grad' (float64 [events, channels, 4]) as requested."""
+    s = sources
+    if i_end is None:
+        i_end = s.n_photons
+    n = i_end - i_begin
+    keep = []
+
+    def arr(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    pos = arr(s.positions, np.float32)
+    offs = arr(s.offsets, np.int64)
+    dirs = arr(s.directions, np.float32)
+    pols = arr(s.polarizations, np.float32)
+    out = {}
+    rec = np.zeros(n, dtype=RECORD_DTYPE) if records else None
+    hm = np.zeros((s.n_events, scene.n_channels), dtype=np.int64) if hit_map else None
+    gr = np.zeros((s.n_events, scene.n_channels, 4), dtype=np.float64) if grad else None
+    n_src = s.n_sources if s.kind == 0 else 0
+    lib().oracle_run(scene.handle, s.kind, s.medium, s.n_photons, n_src, _p(pos), _p(offs),
+                     int(s.count_per_source), 1 if s.per_source_events else 0, _p(dirs), _p(pols),
+                     float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), int(seed),
+                     int(pid_base), int(max_steps), float(eps), int(grad_material), int(i_begin),
+                     int(i_end), _p(rec), _p(hm), _p(gr), int(n_threads))
+    if records:
+        out["records"] = rec
+    if hit_map:
+        out["hit_map"] = hm
+    if grad:
+        out["grad"] = gr
+    return out
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox(_p(c), _p(k), _p(o))
+    return o
+
+
+def u01(x: int) -> float:
+    return lib().oracle_u01(int(x))
+
+
+def sample(kind, seed, pid0, n, in_dir=None, in_pol=None, cyl=(0.0, 0.0, 0.0)):
+    """kind 0 emission, 1 Lambertian about in_dir, 2 Rayleigh from (in_dir, in_pol),
+    3 uniform-cylinder positions (returned in the first array)."""
+    di = None if in_dir is None else np.ascontiguousarray(
+        np.broadcast_to(np.asarray(in_dir, np.float64), (n, 3)))
+    pi = None if in_pol is None else np.ascontiguousarray(
+        np.broadcast_to(np.asarray(in_pol, np.float64), (n, 3)))
+    od = np.zeros((n, 3))
+    op = np.zeros((n, 3))
+    lib().oracle_sample(int(kind), int(seed), int(pid0), int(n), _p(di), _p(pi), float(cyl[0]),
+                        float(cyl[1]), float(cyl[2]), _p(od), _p(op))
+    return od, op
+
+
+def boundary(mode, d, e, n, n1=1.0, n2=1.0, u=0.5):
+    d = np.ascontiguousarray(d, np.float64)
+    e = np.ascontiguousarray(e, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    od, op = np.zeros(3), np.zeros(3)
+    tr = lib().oracle_boundary(int(mode), _p(d), _p(e), _p(n), float(n1), float(n2), float(u),
+                               _p(od), _p(op))
+    return bool(tr), od, op
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

@@ -1,0 +1,777 @@
+// xeoracle.cpp -- plain FP64 CPU reference of the optical-photon transport.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP path is
+// checked against; only the test suite, the smoke check and the benchmark's
+// CPU-baseline leg may load it.  It shares no code, header, table or constant
+// generator with the HIP library: it takes the same *input arrays* (mesh,
+// optical tables, sources) and computes every photon history on its own, one
+// photon at a time, in double precision, with brute-force closest-hit search
+// (an optional plain binary BVH gives the identical answer faster on large
+// meshes; the tests check that equality).
+//
+// What it computes follows the paper's description of the simulated processes
+// (section "Optical properties", table tab:optical, and the validation checks
+// of section "Comparison of Chroma and Geant4"):
+//   * isotropic emission from point sources or from points uniform in the
+//     active volume (the LCE and average-LCE studies);
+//   * bulk absorption with absorption length L_abs, Rayleigh scattering with
+//     scattering length L_Rayleigh (exponential free paths);
+//   * Rayleigh scattering with the dipole angular law that the appendix
+//     (item 3) requires to match theory;
+//   * surfaces whose reflectivity is given explicitly, split into diffuse and
+//     specular parts and independent of the incidence angle, and Fresnel
+//     reflection/refraction (with total internal reflection) only at
+//     boundaries between the dielectrics quartz, LXe and GXe;
+//   * specular reflection that stays defined at normal incidence (appendix
+//     item 1) and a deterministic choice at the junction of two planes
+//     (appendix item 2);
+//   * detection at photosensors: a photon reaching the photosensitive area is
+//     collected with the sensor's detection probability (the LCE definition
+//     of the Z-scan check counts photons reaching that area).
+// Where the paper is silent (random-number schedule, polarization after
+// Fresnel, the self-intersection epsilon, ...) the reading used here is the
+// one documented with the library's public header; each is restated at the
+// function that implements it.
+//
+// Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -shared -fPIC
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <cstdio>
+#include <algorithm>
+#include <limits>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 0.299792458;  // speed of light in vacuum, m/ns
+const double kInf = std::numeric_limits<double>::infinity();
+
+// terminal flags
+enum : int32_t {
+  F_ALIVE = 0, F_DETECT = 1, F_SENSOR_ABSORB = 2, F_SURFACE_ABSORB = 3, F_BULK_ABSORB = 4,
+  F_ESCAPED = 5, F_MAX_STEPS = 6, F_NAN_ABORT = 7, F_GEOMETRY_ERROR = 0x100
+};
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10, written from Salmon, Moraes, Dror and Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two 32x32->64 products
+// with multipliers 0xD2511F53 and 0xCD9E8D57, the Weyl key bumps 0x9E3779B9 and
+// 0xBB67AE85 between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t v[4]; };
+
+U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n1 = uint32_t(p1);
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n3 = uint32_t(p0);
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  return U4{{c0, c1, c2, c3}};
+}
+
+// u = (top 24 bits + 1/2) / 2^24: strictly inside (0, 1), exact in FP32 and FP64.
+double u01(uint32_t x) { return (double(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+// Draw schedule (the paper names no generator): key = the 64-bit seed, counter
+// = (photon id lo, photon id hi, step, sub-stream).  Step 0 is emission
+// (sub 0: direction and polarization, sub 1: position for volume sources);
+// step s >= 1, sub 0: free paths and the surface/Fresnel decision; sub 1:
+// diffuse reflection; sub 2+j: Rayleigh trial j.
+struct Draw { double u[4]; };
+Draw draw(uint64_t seed, uint64_t pid, uint32_t step, uint32_t sub) {
+  U4 r = philox4x32_10(uint32_t(pid), uint32_t(pid >> 32), step, sub,
+                       uint32_t(seed), uint32_t(seed >> 32));
+  return Draw{{u01(r.v[0]), u01(r.v[1]), u01(r.v[2]), u01(r.v[3])}};
+}
+
+// ---------------------------------------------------------------------------
+// vectors
+// ---------------------------------------------------------------------------
+struct V3 { double x, y, z; };
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 normalize(V3 a) { return (1.0 / norm(a)) * a; }
+inline bool finite3(V3 a) { return std::isfinite(a.x) && std::isfinite(a.y) && std::isfinite(a.z); }
+inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// Orthonormal basis (b1, b2, n) for a unit n: the branch-free construction of
+// Duff, Burgess, Christensen, Hery, Kensler, Liani and Villemin, "Building an
+// orthonormal basis, revisited" (JCGT 2017).
+void onb(V3 n, V3& b1, V3& b2) {
+  const double s = std::copysign(1.0, n.z);
+  const double a = -1.0 / (s + n.z);
+  const double b = n.x * n.y * a;
+  b1 = {1.0 + s * n.x * n.x * a, s * b, -s * n.x};
+  b2 = {b, s + n.y * n.y * a, -n.y};
+}
+
+// Isotropic unit vector: cos(theta) = 1 - 2 u0, phi = 2 pi u1.
+V3 isotropic(double u0, double u1) {
+  const double c = 1.0 - 2.0 * u0;
+  const double s = std::sqrt(std::max(0.0, (1.0 - c) * (1.0 + c)));
+  const double ph = 2.0 * kPi * u1;
+  return {s * std::cos(ph), s * std::sin(ph), c};
+}
+
+// Linear polarization at angle 2 pi u in the plane perpendicular to d.
+V3 random_polarization(V3 d, double u) {
+  V3 b1, b2;
+  onb(d, b1, b2);
+  const double ps = 2.0 * kPi * u;
+  return std::cos(ps) * b1 + std::sin(ps) * b2;
+}
+
+// ---------------------------------------------------------------------------
+// scene
+// ---------------------------------------------------------------------------
+struct Surface {
+  double p_detect, p_absorb, r_diffuse, r_specular, p_transmit;
+  int32_t grad_param, flags;
+};
+struct Material { double n, abs_length, rayleigh_length; };
+
+struct BNode { double lo[3], hi[3]; int32_t left, right, first, count; };
+
+struct Scene {
+  std::vector<V3> v0, v1, v2;       // triangle vertices (double copies of the float inputs)
+  std::vector<int32_t> mat_in, mat_out, surf, sensor;
+  std::vector<Material> mats;
+  std::vector<Surface> surfs;
+  std::vector<int32_t> channel;    // sensor -> hit-map column
+  int32_t n_channels = 0;
+  int32_t n_sensors = 0;
+  // optional plain BVH (binary, median split); leaves index `order`
+  bool use_bvh = false;
+  std::vector<BNode> nodes;
+  std::vector<int32_t> order;
+};
+
+// Watertight ray/triangle test of Woop, Benthin and Wald, "Watertight
+// ray/triangle intersection" (JCGT 2013), in double precision, edges
+// inclusive, both faces.  Returns the hit distance or +inf.
+struct Ray { V3 o, d; int kx, ky, kz; double sx, sy, sz; };
+
+Ray make_ray(V3 o, V3 d) {
+  Ray r{o, d, 0, 0, 0, 0, 0, 0};
+  const double ax = std::fabs(d.x), ay = std::fabs(d.y), az = std::fabs(d.z);
+  r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  r.kx = (r.kz + 1) % 3;
+  r.ky = (r.kx + 1) % 3;
+  if (comp(d, r.kz) < 0) std::swap(r.kx, r.ky);
+  r.sx = comp(d, r.kx) / comp(d, r.kz);
+  r.sy = comp(d, r.ky) / comp(d, r.kz);
+  r.sz = 1.0 / comp(d, r.kz);
+  return r;
+}
+
+double intersect(const Ray& r, V3 p0, V3 p1, V3 p2) {
+  const V3 a = p0 - r.o, b = p1 - r.o, c = p2 - r.o;
+  const double ax = comp(a, r.kx) - r.sx * comp(a, r.kz), ay = comp(a, r.ky) - r.sy * comp(a, r.kz);
+  const double bx = comp(b, r.kx) - r.sx * comp(b, r.kz), by = comp(b, r.ky) - r.sy * comp(b, r.kz);
+  const double cx = comp(c, r.kx) - r.sx * comp(c, r.kz), cy = comp(c, r.ky) - r.sy * comp(c, r.kz);
+  const double u = cx * by - cy * bx;
+  const double v = ax * cy - ay * cx;
+  const double w = bx * ay - by * ax;
+  if ((u < 0 || v < 0 || w < 0) && (u > 0 || v > 0 || w > 0)) return kInf;
+  const double det = u + v + w;
+  if (det == 0.0) return kInf;
+  const double az = r.sz * comp(a, r.kz), bz = r.sz * comp(b, r.kz), cz = r.sz * comp(c, r.kz);
+  const double t = (u * az + v * bz + w * cz) / det;
+  return t;
+}
+
+struct Hit { int32_t tri; double t; };
+
+// Closest hit among all triangles other than `skip` with t in (tmin, tmax];
+// equal distances go to the lower triangle index.
+inline void consider(const Scene& sc, const Ray& r, int32_t j, double tmin, Hit& best) {
+  const double t = intersect(r, sc.v0[j], sc.v1[j], sc.v2[j]);
+  if (!(t > tmin) || !(t <= best.t) || !(t < kInf)) return;  // a miss is +inf
+  if (t < best.t || best.tri < 0 || j < best.tri) best = Hit{j, t};
+}
+
+Hit closest_hit_brute(const Scene& sc, V3 o, V3 d, double tmin, double tmax, int32_t skip) {
+  const Ray r = make_ray(o, d);
+  Hit best{-1, tmax};
+  const int32_t nt = int32_t(sc.v0.size());
+  for (int32_t j = 0; j < nt; ++j) {
+    if (j == skip) continue;
+    consider(sc, r, j, tmin, best);
+  }
+  return best;
+}
+
+bool box_hit(const BNode& n, V3 o, V3 inv, double tmin, double tmax) {
+  double t0 = tmin, t1 = tmax;
+  const double oc[3] = {o.x, o.y, o.z}, ic[3] = {inv.x, inv.y, inv.z};
+  for (int k = 0; k < 3; ++k) {
+    double a = (n.lo[k] - oc[k]) * ic[k], b = (n.hi[k] - oc[k]) * ic[k];
+    if (std::isnan(a)) a = -kInf;  // ray parallel to the slab, origin on its face
+    if (std::isnan(b)) b = kInf;
+    if (a > b) std::swap(a, b);
+    t0 = std::max(t0, a);
+    t1 = std::min(t1, b * (1.0 + 1e-12));
+    if (t0 > t1) return false;
+  }
+  return true;
+}
+
+Hit closest_hit_bvh(const Scene& sc, V3 o, V3 d, double tmin, double tmax, int32_t skip) {
+  const Ray r = make_ray(o, d);
+  const V3 inv{1.0 / d.x, 1.0 / d.y, 1.0 / d.z};
+  Hit best{-1, tmax};
+  int32_t stack[128];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const BNode& n = sc.nodes[stack[--sp]];
+    if (!box_hit(n, o, inv, 0.0, best.t)) continue;
+    if (n.count > 0) {
+      for (int32_t k = 0; k < n.count; ++k) {
+        const int32_t j = sc.order[n.first + k];
+        if (j != skip) consider(sc, r, j, tmin, best);
+      }
+    } else {
+      stack[sp++] = n.left;
+      stack[sp++] = n.right;
+    }
+  }
+  return best;
+}
+
+Hit closest_hit(const Scene& sc, V3 o, V3 d, double tmin, double tmax, int32_t skip) {
+  return sc.use_bvh ? closest_hit_bvh(sc, o, d, tmin, tmax, skip)
+                    : closest_hit_brute(sc, o, d, tmin, tmax, skip);
+}
+
+void build_bvh(Scene& sc) {
+  const int32_t nt = int32_t(sc.v0.size());
+  sc.order.resize(nt);
+  for (int32_t i = 0; i < nt; ++i) sc.order[i] = i;
+  std::vector<V3> cen(nt);
+  for (int32_t i = 0; i < nt; ++i) cen[i] = (1.0 / 3.0) * (sc.v0[i] + sc.v1[i] + sc.v2[i]);
+  sc.nodes.clear();
+  sc.nodes.reserve(2 * size_t(nt) + 1);
+  struct Item { int32_t node, first, count; };
+  std::vector<Item> work;
+  sc.nodes.push_back(BNode{});
+  work.push_back({0, 0, nt});
+  while (!work.empty()) {
+    Item it = work.back();
+    work.pop_back();
+    BNode n{};
+    for (int k = 0; k < 3; ++k) { n.lo[k] = kInf; n.hi[k] = -kInf; }
+    double clo[3] = {kInf, kInf, kInf}, chi[3] = {-kInf, -kInf, -kInf};
+    for (int32_t i = it.first; i < it.first + it.count; ++i) {
+      const int32_t j = sc.order[i];
+      for (const V3& p : {sc.v0[j], sc.v1[j], sc.v2[j]})
+        for (int k = 0; k < 3; ++k) {
+          n.lo[k] = std::min(n.lo[k], comp(p, k));
+          n.hi[k] = std::max(n.hi[k], comp(p, k));
+        }
+      for (int k = 0; k < 3; ++k) {
+        clo[k] = std::min(clo[k], comp(cen[j], k));
+        chi[k] = std::max(chi[k], comp(cen[j], k));
+      }
+    }
+    for (int k = 0; k < 3; ++k) {  // pad: a box test must never drop a triangle the exact test hits
+      const double pad = 1e-9 * (1.0 + std::fabs(n.lo[k]) + std::fabs(n.hi[k]));
+      n.lo[k] -= pad;
+      n.hi[k] += pad;
+    }
+    if (it.count <= 4) {
+      n.left = n.right = -1;
+      n.first = it.first;
+      n.count = it.count;
+      sc.nodes[it.node] = n;
+      continue;
+    }
+    int axis = 0;
+    for (int k = 1; k < 3; ++k)
+      if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
+    const int32_t mid = it.first + it.count / 2;
+    std::nth_element(sc.order.begin() + it.first, sc.order.begin() + mid,
+                     sc.order.begin() + it.first + it.count, [&](int32_t a, int32_t b) {
+                       const double ca = comp(cen[a], axis), cb = comp(cen[b], axis);
+                       return ca < cb || (ca == cb && a < b);
+                     });
+    n.left = int32_t(sc.nodes.size());
+    n.right = n.left + 1;
+    n.first = 0;
+    n.count = 0;
+    sc.nodes[it.node] = n;
+    sc.nodes.push_back(BNode{});
+    sc.nodes.push_back(BNode{});
+    work.push_back({n.left, it.first, mid - it.first});
+    work.push_back({n.right, mid, it.first + it.count - mid});
+  }
+}
+
+// ---------------------------------------------------------------------------
+// photon state and interactions
+// ---------------------------------------------------------------------------
+struct Photon {
+  V3 pos, dir, pol;
+  double time;
+  int32_t medium, last_tri, steps, flag, event, sensor;
+  double path_len;      // path length inside the material bound to gradient params 0/1
+  int32_t n_scatter;    // Rayleigh scatters in that material
+  double sum_inv_r;     // sum over reflections on surfaces tagged "reflectivity" of 1/R
+  double sum_inv_t;     // sum over transmissions through surfaces tagged "transparency" of 1/T
+};
+
+// Rayleigh scattering with the dipole law.  A trial direction k' is drawn
+// isotropically and the new polarization is the old one projected onto the
+// plane perpendicular to k'; the trial is kept with probability 1 - (e.k')^2,
+// the squared length of that projection, which is the dipole emission pattern
+// sin^2 of the angle to the polarization.  Averaged over e perpendicular to the
+// old direction this gives (3/8)(1 + cos^2 theta) in the scattering angle.
+// After 64 rejections the 64th trial is kept (probability 3^-64).
+void rayleigh(Photon& p, uint64_t seed, uint64_t pid, uint32_t step) {
+  V3 k{0, 0, 1}, e{1, 0, 0};
+  for (uint32_t j = 0; j < 64; ++j) {
+    const Draw r = draw(seed, pid, step, 2 + j);
+    k = isotropic(r.u[0], r.u[1]);
+    const double ek = dot(p.pol, k);
+    e = p.pol - ek * k;
+    if (r.u[2] < 1.0 - ek * ek) break;
+  }
+  p.dir = k;
+  p.pol = normalize(e);
+}
+
+// Lambertian (diffuse) reflection into the hemisphere of n_out:
+// cos(theta) = sqrt(u0), phi = 2 pi u1; a fresh random linear polarization.
+void lambertian(Photon& p, V3 n_out, const Draw& r) {
+  V3 b1, b2;
+  onb(n_out, b1, b2);
+  const double ct = std::sqrt(r.u[0]);
+  const double st = std::sqrt(std::max(0.0, 1.0 - r.u[0]));
+  const double ph = 2.0 * kPi * r.u[1];
+  p.dir = normalize(st * std::cos(ph) * b1 + st * std::sin(ph) * b2 + ct * n_out);
+  p.pol = random_polarization(p.dir, r.u[2]);
+}
+
+// Mirror reflection about the plane with unit normal n (either orientation):
+// d' = d - 2 (d.n) n and the same for the polarization.  Defined at normal
+// incidence, where it returns -d (appendix item 1).
+void specular(Photon& p, V3 n) {
+  p.dir = normalize(p.dir - (2.0 * dot(p.dir, n)) * n);
+  p.pol = normalize(p.pol - (2.0 * dot(p.pol, n)) * n);
+}
+
+// Fresnel reflection / refraction at a boundary between real refractive
+// indices n1 (incident side) and n2, for a linearly polarized photon.
+// nhat is the unit normal pointing back into the incident medium.  The
+// polarization is split into s (perpendicular to the plane of incidence) and
+// p parts; amplitude coefficients r_s, r_p, t_s, t_p in the Born & Wolf
+// convention; the reflection probability is R = a_s^2 r_s^2 + a_p^2 r_p^2.
+// At normal incidence the plane of incidence is undefined and s is taken
+// along the polarization itself.  Above the critical angle the photon is
+// totally reflected.  Returns true if it was transmitted.
+bool fresnel(Photon& p, V3 nhat, double n1, double n2, double u) {
+  const V3 d = p.dir, e = p.pol;
+  const double ci = -dot(d, nhat);
+  const double eta = n1 / n2;
+  const double st2 = eta * eta * (1.0 - ci * ci);
+  if (st2 >= 1.0) {  // total internal reflection
+    specular(p, nhat);
+    return false;
+  }
+  const double ct = std::sqrt(1.0 - st2);
+  const double rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
+  const double rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
+  const double ts = 2.0 * n1 * ci / (n1 * ci + n2 * ct);
+  const double tp = 2.0 * n1 * ci / (n2 * ci + n1 * ct);
+  V3 sv = cross(d, nhat);
+  const double sl = norm(sv);
+  V3 s = (sl < 1e-6) ? e : (1.0 / sl) * sv;
+  const double as = dot(e, s);
+  const double ap = dot(e, cross(s, d));
+  const double R = as * as * rs * rs + ap * ap * rp * rp;
+  if (u < R) {
+    const V3 dr = normalize(d + (2.0 * ci) * nhat);
+    p.pol = normalize((rs * as) * s + (rp * ap) * cross(s, dr));
+    p.dir = dr;
+    return false;
+  }
+  const V3 dt = normalize(eta * d + (eta * ci - ct) * nhat);
+  p.pol = normalize((ts * as) * s + (tp * ap) * cross(s, dt));
+  p.dir = dt;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// sources
+// ---------------------------------------------------------------------------
+struct Sources {
+  int32_t kind;            // 0 points, 1 uniform cylinder, 2 explicit
+  int32_t medium;
+  int64_t n_photons;
+  int64_t n_sources;
+  const float* positions;
+  const int64_t* offsets;  // may be null: count_per_source photons each
+  int64_t count_per_source;
+  int32_t per_source_events;
+  const float* directions;
+  const float* polarizations;
+  double cyl_radius, cyl_zlo, cyl_zhi;
+};
+
+int64_t source_of(const Sources& s, int64_t i) {
+  if (s.offsets == nullptr) return i / s.count_per_source;
+  // last source whose offset is <= i (sources with zero photons are skipped)
+  int64_t lo = 0, hi = s.n_sources;  // offsets[lo] <= i < offsets[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (s.offsets[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Emission of photon i (launch-local index) with id pid: position from the
+// source, isotropic direction, random linear polarization, t = 0.
+void emit(Photon& p, const Sources& s, int64_t i, uint64_t seed, uint64_t pid) {
+  p.time = 0;
+  p.medium = s.medium;
+  p.last_tri = -1;
+  p.steps = 0;
+  p.flag = F_ALIVE;
+  p.event = 0;
+  p.sensor = -1;
+  p.path_len = 0;
+  p.n_scatter = 0;
+  p.sum_inv_r = 0;
+  p.sum_inv_t = 0;
+  if (s.kind == 2) {
+    p.pos = {s.positions[3 * i], s.positions[3 * i + 1], s.positions[3 * i + 2]};
+    p.dir = normalize(V3{s.directions[3 * i], s.directions[3 * i + 1], s.directions[3 * i + 2]});
+    p.pol = V3{s.polarizations[3 * i], s.polarizations[3 * i + 1], s.polarizations[3 * i + 2]};
+    p.pol = normalize(p.pol - dot(p.pol, p.dir) * p.dir);
+    return;
+  }
+  const Draw r = draw(seed, pid, 0, 0);
+  p.dir = isotropic(r.u[0], r.u[1]);
+  p.pol = random_polarization(p.dir, r.u[2]);
+  if (s.kind == 0) {
+    const int64_t src = source_of(s, i);
+    p.pos = {s.positions[3 * src], s.positions[3 * src + 1], s.positions[3 * src + 2]};
+    p.event = s.per_source_events ? int32_t(src) : 0;
+  } else {
+    // uniform in the cylinder r <= R, z_lo <= z <= z_hi: r = R sqrt(u0), phi = 2 pi u1
+    const Draw q = draw(seed, pid, 0, 1);
+    const double rr = s.cyl_radius * std::sqrt(q.u[0]);
+    const double ph = 2.0 * kPi * q.u[1];
+    p.pos = {rr * std::cos(ph), rr * std::sin(ph), s.cyl_zlo + (s.cyl_zhi - s.cyl_zlo) * q.u[2]};
+  }
+}
+
+struct Params {
+  uint64_t seed;
+  uint64_t pid_base;
+  int32_t max_steps;
+  double eps;
+  int32_t grad_material;
+};
+
+inline double free_path(double length, double u) {
+  return std::isinf(length) ? kInf : -length * std::log(u);
+}
+
+// Transport of one photon until it ends in exactly one terminal state.
+void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
+  for (int32_t step = 1; step <= prm.max_steps; ++step) {
+    p.steps = step;
+    const Material& m = sc.mats[p.medium];
+    const Draw r = draw(prm.seed, pid, uint32_t(step), 0);
+    const double d_abs = free_path(m.abs_length, r.u[0]);
+    const double d_sca = free_path(m.rayleigh_length, r.u[1]);
+    const double d_bulk = std::min(d_abs, d_sca);
+    const Hit h = closest_hit(sc, p.pos, p.dir, prm.eps, d_bulk, p.last_tri);
+    if (h.tri < 0) {
+      if (std::isinf(d_bulk)) { p.flag |= F_ESCAPED; return; }
+      p.pos = p.pos + d_bulk * p.dir;
+      p.time += d_bulk * m.n / kC;
+      if (p.medium == prm.grad_material) p.path_len += d_bulk;
+      if (d_abs <= d_sca) { p.flag |= F_BULK_ABSORB; return; }
+      if (p.medium == prm.grad_material) p.n_scatter += 1;
+      rayleigh(p, prm.seed, pid, uint32_t(step));
+      p.last_tri = -1;
+    } else {
+      const int32_t k = h.tri;
+      p.pos = p.pos + h.t * p.dir;
+      p.time += h.t * m.n / kC;
+      if (p.medium == prm.grad_material) p.path_len += h.t;
+      const V3 N = normalize(cross(sc.v1[k] - sc.v0[k], sc.v2[k] - sc.v0[k]));
+      const bool from_outer = dot(p.dir, N) < 0.0;
+      const int32_t m_from = from_outer ? sc.mat_out[k] : sc.mat_in[k];
+      const int32_t m_to = from_outer ? sc.mat_in[k] : sc.mat_out[k];
+      if (m_from != p.medium) { p.flag |= F_GEOMETRY_ERROR; p.medium = m_from; }
+      const V3 n_back = from_outer ? N : (-1.0) * N;  // unit normal on the arrival side
+      const int32_t si = sc.surf[k];
+      if (si >= 0) {
+        const Surface& s = sc.surfs[si];
+        const bool is_sensor = sc.sensor[k] >= 0;
+        if ((s.flags & 1) && !from_outer) {  // back of a front-only sensor: absorber
+          p.flag |= F_SURFACE_ABSORB;
+          p.last_tri = k;
+          return;
+        }
+        const double u = r.u[2];
+        double c = s.p_detect;
+        if (u < c) {
+          if (is_sensor) { p.flag |= F_DETECT; p.sensor = sc.sensor[k]; }
+          else p.flag |= F_SURFACE_ABSORB;
+          p.last_tri = k;
+          return;
+        }
+        c += s.p_absorb;
+        if (u < c) {
+          if (is_sensor) { p.flag |= F_SENSOR_ABSORB; p.sensor = sc.sensor[k]; }
+          else p.flag |= F_SURFACE_ABSORB;
+          p.last_tri = k;
+          return;
+        }
+        const double r_tot = s.r_diffuse + s.r_specular;
+        c += s.r_diffuse;
+        if (u < c) {
+          lambertian(p, n_back, draw(prm.seed, pid, uint32_t(step), 1));
+          if (s.grad_param == 2) p.sum_inv_r += 1.0 / r_tot;
+        } else if (u < c + s.r_specular) {
+          specular(p, N);
+          if (s.grad_param == 2) p.sum_inv_r += 1.0 / r_tot;
+        } else if (s.p_transmit > 0.0) {
+          p.medium = m_to;
+          if (s.grad_param == 3) p.sum_inv_t += 1.0 / s.p_transmit;
+        } else {  // probabilities summing to just under one: the remainder absorbs
+          p.flag |= (is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB);
+          if (is_sensor) p.sensor = sc.sensor[k];
+          p.last_tri = k;
+          return;
+        }
+      } else {
+        const double n1 = sc.mats[m_from].n, n2 = sc.mats[m_to].n;
+        if (n1 != n2) {
+          if (fresnel(p, n_back, n1, n2, r.u[2])) p.medium = m_to;
+        } else {
+          p.medium = m_to;
+        }
+      }
+      p.last_tri = k;
+    }
+    if (!finite3(p.pos) || !finite3(p.dir) || !finite3(p.pol)) { p.flag |= F_NAN_ABORT; return; }
+  }
+  p.flag |= F_MAX_STEPS;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface used by the tests (ctypes)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+struct OracleRecord {  // one per photon
+  int32_t flag, last_tri, sensor, steps;
+  int32_t event, medium, n_scatter, pad;
+  double pos[3], dir[3], pol[3];
+  double time, path_len, sum_inv_r, sum_inv_t;
+};
+
+void* oracle_scene_create(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                          const int32_t* mat_in, const int32_t* mat_out, const int32_t* surf,
+                          const int32_t* sensor, const float* mats, int32_t n_mats,
+                          const float* surf_p, const int32_t* surf_tags, int32_t n_surfs,
+                          const int32_t* channel_of_sensor, int32_t n_sensors, int32_t n_channels,
+                          int32_t use_bvh) {
+  Scene* sc = new Scene();
+  sc->v0.resize(nt); sc->v1.resize(nt); sc->v2.resize(nt);
+  for (int64_t i = 0; i < nt; ++i) {
+    const int32_t* t = tri + 3 * i;
+    auto V = [&](int32_t j) { return V3{vtx[3 * j], vtx[3 * j + 1], vtx[3 * j + 2]}; };
+    sc->v0[i] = V(t[0]); sc->v1[i] = V(t[1]); sc->v2[i] = V(t[2]);
+  }
+  (void)nv;
+  sc->mat_in.assign(mat_in, mat_in + nt);
+  sc->mat_out.assign(mat_out, mat_out + nt);
+  sc->surf.assign(surf, surf + nt);
+  sc->sensor.assign(sensor, sensor + nt);
+  for (int32_t i = 0; i < n_mats; ++i)
+    sc->mats.push_back(Material{mats[3 * i], mats[3 * i + 1], mats[3 * i + 2]});
+  for (int32_t i = 0; i < n_surfs; ++i) {
+    const float* q = surf_p + 5 * i;
+    sc->surfs.push_back(Surface{q[0], q[1], q[2], q[3], q[4], surf_tags[2 * i], surf_tags[2 * i + 1]});
+  }
+  sc->n_sensors = n_sensors;
+  sc->n_channels = n_channels;
+  sc->channel.resize(n_sensors);
+  for (int32_t i = 0; i < n_sensors; ++i) sc->channel[i] = channel_of_sensor ? channel_of_sensor[i] : i;
+  sc->use_bvh = use_bvh != 0;
+  if (sc->use_bvh) build_bvh(*sc);
+  return sc;
+}
+
+void oracle_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
+
+// Propagate photons with launch-local indices [i_begin, i_end) (photon id =
+// pid_base + i).  Optional outputs: one record per photon (indexed i - i_begin),
+// the hit map [event][channel] (int64, accumulated) and the gradient tallies
+// [event][channel][4] (accumulated).  Returns 0.
+int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int64_t n_sources,
+               const float* positions, const int64_t* offsets, int64_t count_per_source,
+               int32_t per_source_events, const float* directions, const float* polarizations,
+               double cyl_radius, double cyl_zlo, double cyl_zhi, uint64_t seed, uint64_t pid_base,
+               int32_t max_steps, double eps, int32_t grad_material, int64_t i_begin, int64_t i_end,
+               OracleRecord* records, int64_t* hit_map, double* grad, int32_t n_threads) {
+  const Scene& sc = *static_cast<Scene*>(scene);
+  Sources s{kind, medium, n_photons, n_sources, positions, offsets, count_per_source,
+            per_source_events, directions, polarizations, cyl_radius, cyl_zlo, cyl_zhi};
+  Params prm{seed, pid_base, max_steps, eps, grad_material};
+  const Material& gm = sc.mats[grad_material >= 0 ? grad_material : 0];
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+  for (int64_t i = i_begin; i < i_end; ++i) {
+    const uint64_t pid = pid_base + uint64_t(i);
+    Photon p{};
+    emit(p, s, i, seed, pid);
+    transport(sc, prm, pid, p);
+    if (records) {
+      OracleRecord& rec = records[i - i_begin];
+      rec.flag = p.flag; rec.last_tri = p.last_tri; rec.sensor = p.sensor; rec.steps = p.steps;
+      rec.event = p.event; rec.medium = p.medium; rec.n_scatter = p.n_scatter; rec.pad = 0;
+      rec.pos[0] = p.pos.x; rec.pos[1] = p.pos.y; rec.pos[2] = p.pos.z;
+      rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z;
+      rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z;
+      rec.time = p.time; rec.path_len = p.path_len; rec.sum_inv_r = p.sum_inv_r; rec.sum_inv_t = p.sum_inv_t;
+    }
+    if ((p.flag & 0xff) == F_DETECT) {
+      const int64_t cell = int64_t(p.event) * sc.n_channels + sc.channel[p.sensor];
+      if (hit_map) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+        hit_map[cell] += 1;
+      }
+      if (grad) {
+        // score-function (likelihood-ratio) weights of a detected path:
+        // d log P / d L_abs = L / L_abs^2, d log P / d L_R = L / L_R^2 - N_sca / L_R,
+        // d log P / d R = (reflections) / R, d log P / d T = (transmissions) / T.
+        const double sc0 = p.path_len / (gm.abs_length * gm.abs_length);
+        const double sc1 = p.path_len / (gm.rayleigh_length * gm.rayleigh_length)
+                           - double(p.n_scatter) / gm.rayleigh_length;
+        const double g[4] = {std::isfinite(sc0) ? sc0 : 0.0, std::isfinite(sc1) ? sc1 : 0.0,
+                             p.sum_inv_r, p.sum_inv_t};
+        for (int q = 0; q < 4; ++q) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+          grad[cell * 4 + q] += g[q];
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+// ---- hooks for the sampler and boundary tests ----
+void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  U4 r = philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+  for (int k = 0; k < 4; ++k) out[k] = r.v[k];
+}
+
+double oracle_u01(uint32_t x) { return u01(x); }
+
+// kind 0: emission direction+polarization (step 0); kind 1: Lambertian about
+// in_dir (used as the normal), sub 1 of step 1; kind 2: Rayleigh from
+// (in_dir, in_pol) at step 1; kind 3: uniform-cylinder positions (out_dir holds
+// the position).  Photon ids pid0 .. pid0+n-1.
+void oracle_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const double* in_dir,
+                   const double* in_pol, double cyl_r, double zlo, double zhi, double* out_dir,
+                   double* out_pol) {
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t pid = pid0 + uint64_t(i);
+    Photon p{};
+    if (kind == 0) {
+      const Draw r = draw(seed, pid, 0, 0);
+      p.dir = isotropic(r.u[0], r.u[1]);
+      p.pol = random_polarization(p.dir, r.u[2]);
+    } else if (kind == 1) {
+      lambertian(p, V3{in_dir[3 * i], in_dir[3 * i + 1], in_dir[3 * i + 2]}, draw(seed, pid, 1, 1));
+    } else if (kind == 2) {
+      p.dir = V3{in_dir[3 * i], in_dir[3 * i + 1], in_dir[3 * i + 2]};
+      p.pol = V3{in_pol[3 * i], in_pol[3 * i + 1], in_pol[3 * i + 2]};
+      rayleigh(p, seed, pid, 1);
+    } else {
+      Sources s{};
+      s.kind = 1; s.cyl_radius = cyl_r; s.cyl_zlo = zlo; s.cyl_zhi = zhi;
+      emit(p, s, int64_t(i), seed, pid);
+      p.dir = p.pos;
+    }
+    out_dir[3 * i] = p.dir.x; out_dir[3 * i + 1] = p.dir.y; out_dir[3 * i + 2] = p.dir.z;
+    out_pol[3 * i] = p.pol.x; out_pol[3 * i + 1] = p.pol.y; out_pol[3 * i + 2] = p.pol.z;
+  }
+}
+
+// One boundary event: Fresnel (mode 0) or explicit specular (mode 1) for a
+// photon (dir, pol) meeting a plane with unit normal n (any orientation).
+// Returns 1 if transmitted.
+int32_t oracle_boundary(int32_t mode, const double* dir, const double* pol, const double* n,
+                        double n1, double n2, double u, double* out_dir, double* out_pol) {
+  Photon p{};
+  p.dir = V3{dir[0], dir[1], dir[2]};
+  p.pol = V3{pol[0], pol[1], pol[2]};
+  V3 N{n[0], n[1], n[2]};
+  const V3 nb = dot(p.dir, N) < 0 ? N : (-1.0) * N;
+  int32_t tr = 0;
+  if (mode == 0) tr = fresnel(p, nb, n1, n2, u) ? 1 : 0;
+  else specular(p, N);
+  out_dir[0] = p.dir.x; out_dir[1] = p.dir.y; out_dir[2] = p.dir.z;
+  out_pol[0] = p.pol.x; out_pol[1] = p.pol.y; out_pol[2] = p.pol.z;
+  return tr;
+}
+
+// Closest hit for a batch of rays (brute force or the scene's BVH).
+void oracle_closest_hit(void* scene, int64_t n, const double* orig, const double* dir, double tmin,
+                        double tmax, const int32_t* skip, int32_t force_brute, int32_t* out_tri,
+                        double* out_t) {
+  const Scene& sc = *static_cast<Scene*>(scene);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const V3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
+    const V3 d{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+    const int32_t sk = skip ? skip[i] : -1;
+    const Hit h = force_brute ? closest_hit_brute(sc, o, d, tmin, tmax, sk)
+                              : closest_hit(sc, o, d, tmin, tmax, sk);
+    out_tri[i] = h.tri;
+    out_t[i] = h.tri >= 0 ? h.t : kInf;
+  }
+}
+
+int32_t oracle_max_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"
