@@ -1,0 +1,291 @@
+/*
+ * xephot.h -- C ABI of the MI355X (gfx950) optical-photon transport library.
+ *
+ * The library propagates batches of monochromatic scintillation photons
+ * (175 nm) through a triangle-mesh detector and tallies the photons detected
+ * by each photosensor, as the paper's optical simulation of the DARWIN TPC
+ * does (sections "Simulation of the DARWIN detector" and "Optical
+ * properties", table tab:optical).  Processes: bulk absorption (absorption
+ * length), Rayleigh scattering (dipole law, appendix item 3), explicit
+ * angle-independent surfaces split into detect / absorb / diffuse / specular /
+ * transmit, Fresnel reflection and refraction with total internal reflection
+ * at boundaries between dielectrics (quartz, LXe, GXe), and detection at
+ * sensors (the LCE definition of section "Comparison of Chroma and Geant4").
+ *
+ * Conventions for every entry point:
+ *  - Units: metres and nanoseconds.
+ *  - Return value: XP_OK (0) or a negative xp_status.  No C++ exception
+ *    crosses this boundary.  xp_last_error() gives a message.
+ *  - Arguments documented "host" are read during the call and may be freed
+ *    after it returns.  Arguments documented "device" are device memory on the
+ *    context's GPU, owned by the caller, and must stay alive until the work
+ *    queued on the given stream has completed.
+ *  - Per-photon physics failures are not errors: every photon ends with one
+ *    terminal flag (XP_FLAG_*), visible in the optional per-photon records.
+ *  - A context may be used from one host thread at a time.
+ */
+#ifndef XEPHOT_H_
+#define XEPHOT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xp_context xp_context;
+typedef void* xp_stream; /* a hipStream_t (0 = the null stream) */
+
+typedef enum xp_status {
+  XP_OK = 0,
+  XP_ERR_INVALID_ARG = -1, /* a null pointer, a size or an id out of range */
+  XP_ERR_STATE = -2,       /* call out of order (e.g. propagate before build_bvh) */
+  XP_ERR_MESH = -3,        /* mesh failed validation */
+  XP_ERR_HIP = -4,         /* a HIP runtime call failed */
+  XP_ERR_OOM = -5,         /* device or host allocation failed */
+  XP_ERR_UNSUPPORTED = -6  /* valid request this build cannot serve (e.g. BVH too deep) */
+} xp_status;
+
+/* Terminal flags of a photon (low byte) plus the GEOMETRY_ERROR bit. */
+enum {
+  XP_FLAG_DETECT = 1,         /* collected by a sensor (counted in the hit map) */
+  XP_FLAG_SENSOR_ABSORB = 2,  /* reached a sensor's active face, not detected (QE miss) */
+  XP_FLAG_SURFACE_ABSORB = 3, /* absorbed by a surface (or the back of a front-only sensor) */
+  XP_FLAG_BULK_ABSORB = 4,    /* absorbed in the medium */
+  XP_FLAG_ESCAPED = 5,        /* no triangle ahead and no bulk process (mesh leak) */
+  XP_FLAG_MAX_STEPS = 6,      /* still alive after max_steps steps */
+  XP_FLAG_NAN_ABORT = 7,      /* a non-finite position or direction */
+  XP_FLAG_GEOMETRY_ERROR = 0x100 /* arrived from a medium other than the tracked one */
+};
+
+/* ------------------------------------------------------------------------- */
+/* context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle.
+ * The library owns every device copy of geometry and tables it makes; they are
+ * freed by xp_context_destroy.  Errors: XP_ERR_INVALID_ARG, XP_ERR_HIP. */
+int xp_context_create(int hip_device, xp_context** out);
+void xp_context_destroy(xp_context* ctx);
+
+/* Message of the last failed call on ctx, valid until the next call on ctx;
+ * xp_last_error(NULL) gives the calling thread's last message (used when
+ * xp_context_create fails).  Never NULL. */
+const char* xp_last_error(const xp_context* ctx);
+
+/* ------------------------------------------------------------------------- */
+/* geometry and optical tables (the paper's per-component optical properties,
+ * table tab:optical)                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Load an indexed triangle mesh (host arrays, copied).
+ *   vtx        float[nv*3]  vertex coordinates (m)
+ *   tri        int32[nt*3]  vertex indices; the geometric normal
+ *                           (v1-v0) x (v2-v0) points to the triangle's OUTER side
+ *   mat_inner  int32[nt]    material on the inner side, mat_outer on the outer
+ *   surface    int32[nt]    surface id, or -1: no explicit surface (a Fresnel
+ *                           boundary when the refractive indices differ, else
+ *                           the photon passes through)
+ *   sensor     int32[nt]    sensor id, or -1
+ * Validation: nv, nt > 0, nt < 2^31; indices in [0, nv); finite coordinates;
+ * triangle area >= 1e-12 m^2; material ids in [0, 255]; surface ids in
+ * [-1, 65534]; sensor ids >= -1.  Errors: XP_ERR_INVALID_ARG, XP_ERR_MESH.
+ * Replaces any previous mesh and invalidates the BVH. */
+int xp_load_mesh(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                 const int32_t* mat_inner, const int32_t* mat_outer, const int32_t* surface,
+                 const int32_t* sensor);
+
+/* Bulk optical properties of a medium.  Lengths may be INFINITY (no process). */
+typedef struct xp_material {
+  float n;                 /* real refractive index */
+  float abs_length;        /* absorption length L_abs (m), > 0 */
+  float rayleigh_length;   /* Rayleigh scattering length L_Rayleigh (m), > 0 */
+} xp_material;
+
+/* Set the material table (host array of n <= 8 entries, copied).
+ * Errors: XP_ERR_INVALID_ARG (n out of range, a non-positive or NaN value). */
+int xp_set_materials(xp_context* ctx, const xp_material* m, int32_t n);
+
+#define XP_SURF_DETECT_FRONT_ONLY 1 /* detect only photons arriving from the outer side;
+                                       from the inner side the surface absorbs */
+
+/* An explicit surface: the probabilities partition [0, 1) in the order
+ * detect | absorb | diffuse (Lambertian) | specular | transmit, independent of
+ * the angle of incidence; any rounding remainder absorbs.  `grad_param` tags
+ * the surface for the gradient tallies: 2 = reflectivity parameter (scales the
+ * diffuse and specular parts together), 3 = transparency parameter, -1 none. */
+typedef struct xp_surface {
+  float p_detect, p_absorb, r_diffuse, r_specular, p_transmit;
+  int32_t grad_param;
+  int32_t flags;           /* XP_SURF_* */
+} xp_surface;
+
+/* Set the surface table (host array of n <= 16 entries, copied).  Each
+ * entry's probabilities must be in [0, 1] and sum to 1 +- 1e-6.
+ * Errors: XP_ERR_INVALID_ARG. */
+int xp_set_surfaces(xp_context* ctx, const xp_surface* s, int32_t n);
+
+/* Map sensor ids to hit-map columns (host array, copied): detections on
+ * sensor k count into column channel_of_sensor[k] of n_channels.  Without a
+ * call the map is the identity with n_channels = 1 + the largest sensor id.
+ * Errors: XP_ERR_INVALID_ARG (a column outside [0, n_channels)). */
+int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_t n_sensors,
+                       int32_t n_channels);
+
+/* ------------------------------------------------------------------------- */
+/* acceleration structure (the paper names none; this library's own)          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct xp_bvh_options {
+  int32_t max_leaf_size;   /* triangles per leaf, 1..8 (default 4) */
+  int32_t sah_bins;        /* SAH bins per axis, 4..64 (default 32) */
+} xp_bvh_options;
+
+typedef struct xp_bvh_stats {
+  int64_t n_nodes;         /* 4-wide nodes of 128 bytes */
+  int64_t n_triangles;     /* 48-byte triangle records */
+  int32_t depth;           /* levels below the root */
+  int32_t max_stack;       /* worst-case traversal stack entries */
+  int64_t node_bytes, triangle_bytes;
+  double build_seconds;
+} xp_bvh_stats;
+
+/* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
+ * it.  opts may be NULL (defaults).  Must follow xp_load_mesh
+ * (else XP_ERR_STATE).  Synchronizes the device.  Errors: XP_ERR_STATE,
+ * XP_ERR_INVALID_ARG, XP_ERR_OOM, XP_ERR_HIP, XP_ERR_UNSUPPORTED. */
+int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);
+int xp_bvh_stats(const xp_context* ctx, xp_bvh_stats* out);
+
+/* ------------------------------------------------------------------------- */
+/* photon sources                                                             */
+/* ------------------------------------------------------------------------- */
+
+enum {
+  XP_SRC_POINTS = 0,           /* isotropic point sources (the paper's point-source and
+                                  Z-scan runs); photon i belongs to source s with
+                                  offsets[s] <= i < offsets[s+1] */
+  XP_SRC_UNIFORM_CYLINDER = 1, /* each photon at its own uniform point of the cylinder
+                                  r <= cyl_radius, cyl_zlo <= z <= cyl_zhi (the average-LCE
+                                  run: photons uniform in the active volume) */
+  XP_SRC_EXPLICIT = 2          /* given position, direction and polarization per photon */
+};
+
+typedef struct xp_sources {
+  int32_t kind;               /* XP_SRC_* */
+  int32_t medium;             /* material id the photons start in */
+  int64_t n_photons;          /* photons in this launch, >= 0 */
+  int64_t n_sources;          /* POINTS: number of points */
+  const float* positions;     /* device: POINTS float[n_sources*3]; EXPLICIT float[n_photons*3] */
+  const int64_t* offsets;     /* device: POINTS int64[n_sources+1] prefix sums (offsets[0] = 0,
+                                 offsets[n_sources] = n_photons), or NULL: count_per_source each */
+  int64_t count_per_source;   /* POINTS without offsets */
+  int32_t per_source_events;  /* POINTS: 1 = one hit-map row per source, 0 = a single row */
+  int32_t reserved;
+  const float* directions;    /* device: EXPLICIT float[n_photons*3] (unit) */
+  const float* polarizations; /* device: EXPLICIT float[n_photons*3] (made transverse) */
+  float cyl_radius, cyl_zlo, cyl_zhi; /* UNIFORM_CYLINDER */
+} xp_sources;
+
+/* ------------------------------------------------------------------------- */
+/* propagation                                                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct xp_run_params {
+  uint64_t seed;           /* Philox-4x32-10 key */
+  uint64_t pid_base;       /* photon i of this launch has id pid_base + i; its random
+                              numbers depend only on (seed, id) */
+  int32_t max_steps;       /* steps before XP_FLAG_MAX_STEPS (default 10000 if <= 0) */
+  float eps;               /* hits on triangles other than the last one are taken for
+                              distances > eps (m); 0 is the default */
+  int32_t grad_material;   /* material whose L_abs / L_Rayleigh are gradient params 0 / 1
+                              (-1: none) */
+  int32_t reserved;
+} xp_run_params;
+
+typedef struct xp_launch_cfg {
+  int32_t block_size;      /* threads per workgroup: 64, 128 or 256 (0 = default) */
+  int32_t blocks_per_cu;   /* resident workgroups per CU (0 = as many as fit) */
+  int32_t chunk;           /* photon ids claimed per wave refill (0 = default 64) */
+  int32_t lds_levels;      /* BVH levels staged in LDS, 0..4 (-1 = default) */
+} xp_launch_cfg;
+
+/* One per photon (indexed by the launch-local photon index), written when
+ * requested.  96 bytes. */
+typedef struct xp_photon_record {
+  int32_t flag, last_tri, sensor, steps;
+  int32_t event, medium, n_scatter, reserved;
+  float pos[3];  float time;       /* final position (m), time of flight (ns) */
+  float dir[3];  float path_len;   /* final direction; path length in grad_material */
+  float pol[3];  float sum_inv_r;  /* final polarization; sum of 1/R over tagged reflections */
+  float sum_inv_t; float pad[3];   /* sum of 1/T over tagged transmissions */
+} xp_photon_record;
+
+/* Launch the transport of src->n_photons photons on `stream` (asynchronous).
+ *   d_hit_map  device int32 [n_events * n_channels], ACCUMULATED (the caller
+ *              zeroes it); n_events = n_sources if per_source_events else 1.
+ *              May be NULL.
+ *   d_grad     device double [n_events * n_channels * 4] or NULL: accumulates,
+ *              per detected photon, its score-function weights for
+ *              (L_abs, L_Rayleigh of grad_material, reflectivity, transparency),
+ *              i.e. the Jacobian of the expected hits.
+ *   d_records  device xp_photon_record [n_photons] or NULL.
+ *   d_stats    device uint64 [16] or NULL: ACCUMULATES counters
+ *              [0..7] photons per terminal flag (index = flag low byte),
+ *              [8] GEOMETRY_ERROR photons, [9] steps, [10] BVH nodes visited,
+ *              [11] triangles tested (counting mode costs time).
+ *   lc         NULL = the context's tuned or default configuration.
+ * Errors: XP_ERR_STATE (no BVH / tables), XP_ERR_INVALID_ARG, XP_ERR_HIP.
+ * Concurrency: calls on one context use a ring of 64 work counters; at most
+ * 64 launches of one context may be in flight at a time. */
+int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                 int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                 uint64_t* d_stats, const xp_launch_cfg* lc, xp_stream stream);
+
+/* Backward pass of the expected hit map with respect to the four parameters,
+ * by replaying the same photon histories (same seed and photon ids, so no
+ * path storage):  d_grad_params[p] += sum over detected photons of
+ * d_grad_hits[event * n_channels + channel] * score_p.
+ *   d_grad_hits    device float [n_events * n_channels]
+ *   d_grad_params  device double [4], ACCUMULATED
+ * Errors as xp_propagate. */
+int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                const float* d_grad_hits, double* d_grad_params, const xp_launch_cfg* lc,
+                xp_stream stream);
+
+/* Pick the fastest launch configuration on a sample of `src` (at most
+ * sample_photons photons) by timing candidates; stores it in the context (used
+ * when lc is NULL) and in *out (may be NULL).  Integer results never depend on
+ * the choice.  Synchronizes the stream.  Errors as xp_propagate. */
+int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                int64_t sample_photons, xp_launch_cfg* out, xp_stream stream);
+
+/* ------------------------------------------------------------------------- */
+/* test hooks                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Closest hit for n rays (device arrays): orig/dir float[n*3], skip int32[n]
+ * (triangle to ignore, -1 none; may be NULL); out_tri int32[n] (mesh triangle
+ * index or -1), out_t float[n].  Hits are taken for t in (tmin, tmax], ties go
+ * to the lower triangle index.  brute != 0 tests every triangle instead of
+ * traversing the BVH. */
+int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* dir,
+                   const int32_t* skip, float tmin, float tmax, int32_t brute, int32_t* out_tri,
+                   float* out_t, xp_stream stream);
+
+/* Device samplers (device arrays of n rows): kind 0 emission direction and
+ * polarization, 1 Lambertian about in_dir, 2 Rayleigh from (in_dir, in_pol),
+ * 3 uniform-cylinder positions (in out_dir).  Photon ids pid0 .. pid0+n-1 with
+ * the same random-number schedule as xp_propagate. */
+int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
+              const float* in_pol, float cyl_radius, float cyl_zlo, float cyl_zhi, float* out_dir,
+              float* out_pol, xp_stream stream);
+
+/* Library version string. */
+const char* xp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XEPHOT_H_ */

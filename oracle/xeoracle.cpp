@@ -80,8 +80,9 @@ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
   return U4{{c0, c1, c2, c3}};
 }
 
-// u = (top 24 bits + 1/2) / 2^24: strictly inside (0, 1), exact in FP32 and FP64.
-double u01(uint32_t x) { return (double(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+// u = (top 23 bits + 1/2) / 2^23 = (2k + 1) / 2^24 with k < 2^23: strictly inside
+// (0, 1) and exactly representable in FP32 as well as FP64.
+double u01(uint32_t x) { return (double(x >> 9) + 0.5) * (1.0 / 8388608.0); }
 
 // Draw schedule (the paper names no generator): key = the 64-bit seed, counter
 // = (photon id lo, photon id hi, step, sub-stream).  Step 0 is emission

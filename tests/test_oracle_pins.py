@@ -34,14 +34,19 @@ def test_philox_known_answers(oracle_lib):
 
 
 def test_u01_open_interval_and_exact(oracle_lib):
-    assert oracle_lib.u01(0) == 0.5 / 2 ** 24
-    assert oracle_lib.u01(0xFFFFFFFF) == (2 ** 24 - 0.5) / 2 ** 24
+    assert oracle_lib.u01(0) == 2.0 ** -24
+    assert oracle_lib.u01(0xFFFFFFFF) == 1.0 - 2.0 ** -24
     assert oracle_lib.u01(0xFFFFFFFF) < 1.0
-    # only the top 24 bits matter
-    assert oracle_lib.u01(0x12345678) == oracle_lib.u01(0x123456FF)
-    x = 0xABCDEF12
-    assert oracle_lib.u01(x) == ((x >> 8) + 0.5) / 2 ** 24
-    assert np.float32(oracle_lib.u01(x)) == oracle_lib.u01(x)  # exact in FP32
+    # only the top 23 bits matter
+    assert oracle_lib.u01(0x12345600) == oracle_lib.u01(0x123457FF)
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.integers(0, 2 ** 32, 10_000, dtype=np.uint64),
+                         [0, 1, 511, 512, 2 ** 31, 2 ** 32 - 512, 2 ** 32 - 1]])
+    for x in xs:
+        u = oracle_lib.u01(int(x))
+        assert u == ((int(x) >> 9) + 0.5) / 2 ** 23
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u  # exactly representable in FP32 (compared in FP64)
 
 
 # ---------------------------------------------------------------------------
