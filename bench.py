@@ -1,0 +1,242 @@
+"""Throughput benchmark of the photon transport on one MI355X.
+
+One step = one launch of the whole transport (on-device emission, BVH
+closest-hit traversal, bulk absorption, Rayleigh scattering, surface and
+Fresnel interactions, detection tally) over a batch of photons on the
+DARWIN-scale synthetic TPC (about 4.75e5 triangles, 1,778 sensors), each
+photon at its own uniform point of the active volume.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--photons N]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photons propagated/sec on DARWIN-scale TPC mesh; gradient-pass overhead vs forward"
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+NODE_BYTES, TRI_BYTES = 128, 48
+KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
+                  "paper_2203_14354_amd/csrc/xp_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(photons_per_launch: int):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources at the same launch size; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", text)
+    m_n = re.search(r"photons_per_launch:\s*(\d+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_n and m_b):
+        return None
+    if m_hash.group(1) != kernel_hash() or int(m_n.group(1)) != photons_per_launch:
+        return None
+    return float(m_b.group(1))
+
+
+def timed_launches(fn, n, torch):
+    """Run fn() n times; per-launch HIP event durations (s) and wall time (s)."""
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) * 1e-3 for a, b in evs], wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=100_000_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the gradient-overhead and batched measurements")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
+                    help="also run one device-to-device copy of BYTES bytes (a known-traffic "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the transport has no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_14354_amd import workloads as W
+    from paper_2203_14354_amd.runtime import Detector
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    if args.calibration_copy > 0:
+        a = torch.ones(args.calibration_copy // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    mesh = W.darwin()
+    det = Detector(mesh, device=0)
+    wl = W.darwin_tpc(n_photons=args.photons, seed=args.seed, mesh=mesh)
+    ds = det.sources(wl.sources)
+    hit_map = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+    N = wl.sources.n_photons
+    step_no = [0]
+
+    def step():
+        hit_map.zero_()
+        det.propagate(ds, seed=args.seed, pid_base=step_no[0] * N, hit_map=hit_map)
+        step_no[0] += 1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    durations, wall = timed_launches(step, args.steps, torch)
+    ms_per_step = wall / args.steps * 1e3
+    value = N * args.steps / wall
+
+    # counting launch (untimed): nodes visited, triangles tested, steps, flags
+    cnt = det.propagate(ds, seed=args.seed, pid_base=0, stats=True)
+    torch.cuda.synchronize()
+    st = cnt["stats"].cpu().tolist()
+    n_steps, n_nodes, n_tris = st[9], st[10], st[11]
+    alg_bytes = NODE_BYTES * n_nodes + TRI_BYTES * n_tris
+    kern_s = statistics.mean(durations)
+    achieved = alg_bytes / kern_s
+    traffic = measured_traffic(N)
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": traffic,
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel": "propagate_kernel<forward>", "avg_launch_s": kern_s}
+
+    extras = {}
+    if not args.no_extras:
+        extras.update(gradient_overhead(torch, W, Detector, dev))
+        extras.update(batched_vs_plain(torch, W, Detector, dev))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(W, mesh, args.seed, args.cpu_sample)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "photons/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "darwin_tpc", "photons_per_step": N,
+                   "triangles": int(mesh.n_triangles), "sensors": int(mesh.n_sensors),
+                   "source": "uniform in r<=1.299 m, -2.597<=z<=-0.001 m, isotropic, 175 nm",
+                   "bvh_nodes": det.bvh["n_nodes"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_launch": {"steps_per_photon": n_steps / N, "nodes_per_step": n_nodes / n_steps,
+                       "triangles_per_step": n_tris / n_steps,
+                       "detected_fraction": st[1] / N, "bulk_absorbed_fraction": st[4] / N,
+                       "surface_absorbed_fraction": st[3] / N,
+                       "geometry_errors": st[8], "escaped": st[5], "max_steps": st[6],
+                       "nan_aborts": st[7]},
+        "kernel_sources_sha256_16": kernel_hash(),
+    }
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+def gradient_overhead(torch, W, Detector, dev):
+    """Differentiable workload (small TPC + transparent plane, 1e7 photons):
+    forward with fused FP64 gradient tallies, and the backward replay, each
+    against plain forward transport on the same GPU."""
+    wl = W.differentiable(photons_per_point=1_000_000)
+    det = Detector(wl.mesh, device=0)
+    ds = det.sources(wl.sources)
+    hm = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+    g = torch.zeros((1, det.n_channels, 4), dtype=torch.float64, device=dev)
+    gh = torch.ones((1, det.n_channels), dtype=torch.float32, device=dev)
+    gp = torch.zeros(4, dtype=torch.float64, device=dev)
+    runs = {
+        "forward": lambda: det.propagate(ds, seed=1, hit_map=hm),
+        "forward_fused_tallies": lambda: det.propagate(ds, seed=1, hit_map=hm, grad=g),
+        "backward_replay": lambda: det.backward(ds, gh, seed=1, grad_params=gp),
+    }
+    t = {}
+    for k, fn in runs.items():
+        fn()
+        d, _ = timed_launches(fn, 5, torch)
+        t[k] = statistics.median(d)
+    n = wl.sources.n_photons
+    return {"gradient_overhead": {
+        "workload": "differentiable: small TPC + transparent plane, 1e7 photons",
+        "forward_photons_per_s": n / t["forward"],
+        "fused_tallies_over_forward": t["forward_fused_tallies"] / t["forward"],
+        "forward_plus_backward_over_forward": (t["forward"] + t["backward_replay"]) / t["forward"],
+        "backward_replay_over_forward": t["backward_replay"] / t["forward"]}}
+
+
+def batched_vs_plain(torch, W, Detector, dev):
+    """4096 log-normal S1 sources in one persistent launch vs plain forward of
+    the same photon count from one source list without per-event maps."""
+    wl = W.batched_s1()
+    det = Detector(wl.mesh, device=0)
+    ds = det.sources(wl.sources)
+    n = wl.sources.n_photons
+    hm = torch.zeros((wl.sources.n_events, det.n_channels), dtype=torch.int32, device=dev)
+    plain_src = W.point_sources(wl.sources.positions, counts=None,
+                                count_per_source=int(-(-n // len(wl.sources.positions))))
+    dp = det.sources(plain_src)
+    hm1 = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+    fb = lambda: det.propagate(ds, seed=2, hit_map=hm)
+    fp = lambda: det.propagate(dp, seed=2, hit_map=hm1, n_photons=n)
+    fb()
+    fp()
+    db, _ = timed_launches(fb, 5, torch)
+    dpl, _ = timed_launches(fp, 5, torch)
+    return {"batched_s1": {"workload": f"4096 log-normal sources, {n} photons, per-event maps",
+                           "photons_per_s": n / statistics.median(db),
+                           "plain_forward_photons_per_s": n / statistics.median(dpl)}}
+
+
+def cpu_baseline(W, mesh, seed, sample):
+    """The FP64 oracle, as it stands, on the first `sample` photons of the same workload."""
+    import oracle
+    sc = oracle.Scene(mesh, use_bvh=True)
+    src = W.darwin_tpc(n_photons=sample, seed=seed, mesh=mesh).sources
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.run(sc, src, seed=seed, records=False, hit_map=True)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
+            "sample": f"photon ids 0..{sample - 1} of the DARWIN-scale workload "
+                      f"(FP64, OpenMP, {threads} threads), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -148,14 +148,14 @@ typedef struct xp_bvh_stats {
   int32_t max_stack;       /* worst-case traversal stack entries */
   int64_t node_bytes, triangle_bytes;
   double build_seconds;
-} xp_bvh_stats;
+} xp_bvh_info;
 
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
  * it.  opts may be NULL (defaults).  Must follow xp_load_mesh
  * (else XP_ERR_STATE).  Synchronizes the device.  Errors: XP_ERR_STATE,
  * XP_ERR_INVALID_ARG, XP_ERR_OOM, XP_ERR_HIP, XP_ERR_UNSUPPORTED. */
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);
-int xp_bvh_stats(const xp_context* ctx, xp_bvh_stats* out);
+int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
 
 /* ------------------------------------------------------------------------- */
 /* photon sources                                                             */
@@ -200,7 +200,10 @@ typedef struct xp_run_params {
                               distances > eps (m); 0 is the default */
   int32_t grad_material;   /* material whose L_abs / L_Rayleigh are gradient params 0 / 1
                               (-1: none) */
-  int32_t reserved;
+  float surface_offset;    /* m: after a surface interaction the photon restarts this far
+                              from the surface along its normal, on the side it leaves
+                              toward (recommended 2e-6: above the FP32 rounding of
+                              positions up to ~3 m, below any feature of the meshes) */
 } xp_run_params;
 
 typedef struct xp_launch_cfg {

@@ -60,7 +60,7 @@ def lib():
         L.oracle_scene_destroy.argtypes = [P]
         L.oracle_run.restype = ctypes.c_int
         L.oracle_run.argtypes = [P, I32, I32, I64, I64, P, P, I64, I32, P, P, D, D, D, U64, U64,
-                                 I32, D, I32, I64, I64, P, P, P, I32]
+                                 I32, D, I32, D, I64, I64, P, P, P, I32]
         L.oracle_philox.argtypes = [P, P, P]
         L.oracle_u01.restype = D
         L.oracle_u01.argtypes = [ctypes.c_uint32]
@@ -124,8 +124,12 @@ class Scene:
         return tri, t
 
 
+SURFACE_OFFSET = 2e-6  # m
+
+
 def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, grad_material=0,
-        i_begin=0, i_end=None, records=True, hit_map=True, grad=False, n_threads=0):
+        i_begin=0, i_end=None, records=True, hit_map=True, grad=False, n_threads=0,
+        surface_offset=SURFACE_OFFSET):
     """Propagate launch-local photons [i_begin, i_end).  Returns a dict with
     'records' (RECORD_DTYPE array), 'hit_map' (int64 [events, channels]) and
     'grad' (float64 [events, channels, 4]) as requested."""
@@ -154,7 +158,8 @@ def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, gr
     lib().oracle_run(scene.handle, s.kind, s.medium, s.n_photons, n_src, _p(pos), _p(offs),
                      int(s.count_per_source), 1 if s.per_source_events else 0, _p(dirs), _p(pols),
                      float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), int(seed),
-                     int(pid_base), int(max_steps), float(eps), int(grad_material), int(i_begin),
+                     int(pid_base), int(max_steps), float(eps), int(grad_material),
+                     float(surface_offset), int(i_begin),
                      int(i_end), _p(rec), _p(hm), _p(gr), int(n_threads))
     if records:
         out["records"] = rec

@@ -110,11 +110,15 @@ inline V3 normalize(V3 a) { return (1.0 / norm(a)) * a; }
 inline bool finite3(V3 a) { return std::isfinite(a.x) && std::isfinite(a.y) && std::isfinite(a.z); }
 inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 
-// Orthonormal basis (b1, b2, n) for a unit n: the branch-free construction of
-// Duff, Burgess, Christensen, Hery, Kensler, Liani and Villemin, "Building an
-// orthonormal basis, revisited" (JCGT 2017).
+// Orthonormal basis (b1, b2, n) for a unit n: the construction of Duff,
+// Burgess, Christensen, Hery, Kensler, Liani and Villemin, "Building an
+// orthonormal basis, revisited" (JCGT 2017), with its two branches (s = +1,
+// valid for n_z > -1; s = -1, valid for n_z < 1) switched at n_z = -1/2 instead
+// of at the sign of n_z.  Detector walls have normals in the xy plane, where
+// the sign of n_z is rounding noise; the threshold keeps the basis a function
+// of the geometry.
 void onb(V3 n, V3& b1, V3& b2) {
-  const double s = std::copysign(1.0, n.z);
+  const double s = n.z >= -0.5 ? 1.0 : -1.0;
   const double a = -1.0 / (s + n.z);
   const double b = n.x * n.y * a;
   b1 = {1.0 + s * n.x * n.x * a, s * b, -s * n.x};
@@ -482,12 +486,20 @@ void emit(Photon& p, const Sources& s, int64_t i, uint64_t seed, uint64_t pid) {
   }
 }
 
+// eps: hits on triangles other than the last one count for t > eps.
+// surface_offset: after a (non-terminal) surface interaction the photon
+// restarts this far from the surface, along the normal on the side it leaves
+// toward.  This keeps a photon that lands near the shared edge of two coplanar
+// triangles from re-hitting the neighbour at t ~ 0 from the wrong side, while
+// a neighbouring face of a concave corner still lies ahead of it (a window of
+// t values below eps would let such a photon pass through that face).
 struct Params {
   uint64_t seed;
   uint64_t pid_base;
   int32_t max_steps;
   double eps;
   int32_t grad_material;
+  double surface_offset;
 };
 
 inline double free_path(double length, double u) {
@@ -550,6 +562,7 @@ void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
         }
         const double r_tot = s.r_diffuse + s.r_specular;
         c += s.r_diffuse;
+        bool through = false;
         if (u < c) {
           lambertian(p, n_back, draw(prm.seed, pid, uint32_t(step), 1));
           if (s.grad_param == 2) p.sum_inv_r += 1.0 / r_tot;
@@ -558,6 +571,7 @@ void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
           if (s.grad_param == 2) p.sum_inv_r += 1.0 / r_tot;
         } else if (s.p_transmit > 0.0) {
           p.medium = m_to;
+          through = true;
           if (s.grad_param == 3) p.sum_inv_t += 1.0 / s.p_transmit;
         } else {  // probabilities summing to just under one: the remainder absorbs
           p.flag |= (is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB);
@@ -565,13 +579,13 @@ void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
           p.last_tri = k;
           return;
         }
+        p.pos = p.pos + (through ? -prm.surface_offset : prm.surface_offset) * n_back;
       } else {
         const double n1 = sc.mats[m_from].n, n2 = sc.mats[m_to].n;
-        if (n1 != n2) {
-          if (fresnel(p, n_back, n1, n2, r.u[2])) p.medium = m_to;
-        } else {
-          p.medium = m_to;
-        }
+        bool through = true;
+        if (n1 != n2) through = fresnel(p, n_back, n1, n2, r.u[2]);
+        if (through) p.medium = m_to;
+        p.pos = p.pos + (through ? -prm.surface_offset : prm.surface_offset) * n_back;
       }
       p.last_tri = k;
     }
@@ -637,12 +651,13 @@ int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int
                const float* positions, const int64_t* offsets, int64_t count_per_source,
                int32_t per_source_events, const float* directions, const float* polarizations,
                double cyl_radius, double cyl_zlo, double cyl_zhi, uint64_t seed, uint64_t pid_base,
-               int32_t max_steps, double eps, int32_t grad_material, int64_t i_begin, int64_t i_end,
-               OracleRecord* records, int64_t* hit_map, double* grad, int32_t n_threads) {
+               int32_t max_steps, double eps, int32_t grad_material, double surface_offset,
+               int64_t i_begin, int64_t i_end, OracleRecord* records, int64_t* hit_map,
+               double* grad, int32_t n_threads) {
   const Scene& sc = *static_cast<Scene*>(scene);
   Sources s{kind, medium, n_photons, n_sources, positions, offsets, count_per_source,
             per_source_events, directions, polarizations, cyl_radius, cyl_zlo, cyl_zhi};
-  Params prm{seed, pid_base, max_steps, eps, grad_material};
+  Params prm{seed, pid_base, max_steps, eps, grad_material, surface_offset};
   const Material& gm = sc.mats[grad_material >= 0 ? grad_material : 0];
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -724,6 +739,7 @@ void oracle_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const 
       s.kind = 1; s.cyl_radius = cyl_r; s.cyl_zlo = zlo; s.cyl_zhi = zhi;
       emit(p, s, int64_t(i), seed, pid);
       p.dir = p.pos;
+      p.pol = V3{0.0, 0.0, 0.0};
     }
     out_dir[3 * i] = p.dir.x; out_dir[3 * i + 1] = p.dir.y; out_dir[3 * i + 2] = p.dir.z;
     out_pol[3 * i] = p.pol.x; out_pol[3 * i + 1] = p.pol.y; out_pol[3 * i + 2] = p.pol.z;

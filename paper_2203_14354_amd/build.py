@@ -1,0 +1,61 @@
+"""Build the gfx950 transport library ``libxephot.so`` in-tree with hipcc.
+
+Device code is compiled for gfx950 only, with packed-FP32 instruction
+selection disabled (``-packed-fp32-ops``) and hardware floating-point atomics
+(``-munsafe-fp-atomics``) for the FP64 gradient tallies.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libxephot.so")
+BUILD_DIR = os.path.join(ROOT, "_build")
+
+HOST_SOURCES = ["api.cpp", "bvh.cpp"]
+DEVICE_SOURCES = ["propagate.hip"]
+ARCH = "gfx950"
+
+
+def _hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("command failed: " + " ".join(cmd))
+    return r
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
+    dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    objs = []
+    for s in HOST_SOURCES + DEVICE_SOURCES:
+        o = os.path.join(BUILD_DIR, s + ".o")
+        _run([hipcc, *common, *dev, "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

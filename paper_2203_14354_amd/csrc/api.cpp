@@ -1,0 +1,636 @@
+// api.cpp -- the C ABI of the photon-transport library (declared in
+// include/xephot.h): context, validation, optical tables, BVH upload, launches
+// and the launch-configuration autotuner.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "xp_internal.h"
+
+namespace xp {
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_depth, int block);
+}
+
+struct xp_context {
+  int device = 0;
+  int n_cu = 0;
+  size_t max_lds = 0;
+  std::string err;
+  // mesh (host copy)
+  bool mesh_loaded = false;
+  std::vector<float> vtx;
+  std::vector<int32_t> tri, mat_in, mat_out, surf, sensor;
+  int32_t max_mat = -1, max_surf = -1, max_sensor = -1;
+  // tables
+  std::vector<xp_material> mats;
+  std::vector<xp_surface> surfs;
+  std::vector<int32_t> channel;
+  int32_t n_channels = 0;
+  bool channel_set = false;
+  // device state
+  bool bvh_built = false;
+  xp::BvhResult bvh;
+  xp_bvh_info stats{};
+  xp::Node4* d_nodes = nullptr;
+  xp::TriRec* d_tris = nullptr;
+  int32_t* d_channel = nullptr;
+  int32_t d_channel_len = 0;
+  unsigned long long* d_counters = nullptr;
+  unsigned ring_next = 0;
+  bool tuned = false;
+  xp_launch_cfg tuned_cfg{};
+};
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+int fail(xp_context* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  g_thread_err = msg;
+  return code;
+}
+
+int hip_fail(xp_context* ctx, hipError_t e, const char* what) {
+  return fail(ctx, e == hipErrorOutOfMemory ? XP_ERR_OOM : XP_ERR_HIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+  int old = -1;
+  hipError_t status = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) status = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+int upload_channel_map(xp_context* ctx) {
+  std::vector<int32_t> map;
+  int32_t nch;
+  if (ctx->channel_set) {
+    map = ctx->channel;
+    nch = ctx->n_channels;
+  } else {
+    const int32_t ns = std::max(ctx->max_sensor + 1, 1);
+    map.resize(ns);
+    for (int32_t i = 0; i < ns; ++i) map[i] = i;
+    nch = ns;
+  }
+  if (map.empty()) map.push_back(0);
+  dfree(ctx->d_channel);
+  hipError_t e = hipMalloc(&ctx->d_channel, map.size() * sizeof(int32_t));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(channel map)");
+  e = hipMemcpy(ctx->d_channel, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(channel map)");
+  ctx->d_channel_len = int32_t(map.size());
+  ctx->n_channels = nch;
+  return XP_OK;
+}
+
+xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3}; }
+
+// Validates (ctx, src, rp) for a launch and fills the kernel arguments.
+int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+            const xp_launch_cfg* lc_in, xp::LaunchArgs& a, xp_launch_cfg& lc, int& grid) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!src || !rp) return fail(ctx, XP_ERR_INVALID_ARG, "null sources or run parameters");
+  if (!ctx->bvh_built) return fail(ctx, XP_ERR_STATE, "xp_build_bvh has not been called");
+  if (int32_t(ctx->mats.size()) <= ctx->max_mat)
+    return fail(ctx, XP_ERR_STATE, "material table does not cover the mesh's material ids");
+  if (int32_t(ctx->surfs.size()) <= ctx->max_surf)
+    return fail(ctx, XP_ERR_STATE, "surface table does not cover the mesh's surface ids");
+  if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
+    return fail(ctx, XP_ERR_STATE, "channel map does not cover the mesh's sensor ids");
+  if (src->n_photons < 0) return fail(ctx, XP_ERR_INVALID_ARG, "n_photons < 0");
+  if (src->medium < 0 || src->medium >= int32_t(ctx->mats.size()))
+    return fail(ctx, XP_ERR_INVALID_ARG, "source medium is not a material id");
+  if (rp->grad_material < -1 || rp->grad_material >= int32_t(ctx->mats.size()))
+    return fail(ctx, XP_ERR_INVALID_ARG, "grad_material out of range");
+  if (!(rp->eps >= 0.0f) || !std::isfinite(rp->eps))
+    return fail(ctx, XP_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (!(rp->surface_offset >= 0.0f) || !(rp->surface_offset < 1e-2f))
+    return fail(ctx, XP_ERR_INVALID_ARG, "surface_offset must be in [0, 1e-2) m");
+  switch (src->kind) {
+    case XP_SRC_POINTS:
+      if (!src->positions || src->n_sources <= 0)
+        return fail(ctx, XP_ERR_INVALID_ARG, "POINTS needs positions and n_sources > 0");
+      if (!src->offsets) {
+        if (src->count_per_source <= 0)
+          return fail(ctx, XP_ERR_INVALID_ARG, "POINTS without offsets needs count_per_source > 0");
+        if (src->n_photons > src->n_sources * src->count_per_source)
+          return fail(ctx, XP_ERR_INVALID_ARG, "n_photons exceeds n_sources * count_per_source");
+      }
+      if (src->per_source_events && src->n_sources > INT32_MAX)
+        return fail(ctx, XP_ERR_INVALID_ARG, "too many events");
+      break;
+    case XP_SRC_UNIFORM_CYLINDER:
+      if (!finite_pos(src->cyl_radius) || !std::isfinite(src->cyl_zlo) ||
+          !std::isfinite(src->cyl_zhi) || src->cyl_zhi < src->cyl_zlo)
+        return fail(ctx, XP_ERR_INVALID_ARG, "bad cylinder");
+      break;
+    case XP_SRC_EXPLICIT:
+      if (!src->positions || !src->directions || !src->polarizations)
+        return fail(ctx, XP_ERR_INVALID_ARG, "EXPLICIT needs positions, directions, polarizations");
+      break;
+    default:
+      return fail(ctx, XP_ERR_INVALID_ARG, "unknown source kind");
+  }
+  lc = lc_in ? *lc_in : (ctx->tuned ? ctx->tuned_cfg : default_cfg());
+  if (lc.block_size == 0) lc.block_size = 256;
+  if (lc.chunk <= 0) lc.chunk = 64;
+  if (lc.lds_levels < 0) lc.lds_levels = 3;
+  if (lc.block_size != 64 && lc.block_size != 128 && lc.block_size != 256)
+    return fail(ctx, XP_ERR_INVALID_ARG, "block_size must be 64, 128 or 256");
+  if (lc.lds_levels > 4) return fail(ctx, XP_ERR_INVALID_ARG, "lds_levels must be <= 4");
+  if (lc.chunk > (1 << 20)) return fail(ctx, XP_ERR_INVALID_ARG, "chunk too large");
+
+  std::memset(&a, 0, sizeof(a));
+  a.nodes = ctx->d_nodes;
+  a.tris = ctx->d_tris;
+  a.channel_of_sensor = ctx->d_channel;
+  const int levels = std::min<int>(lc.lds_levels, int(ctx->bvh.level_end.size()));
+  a.n_lds_nodes = levels > 0 ? ctx->bvh.level_end[levels - 1] : 0;
+  a.stack_depth = ctx->bvh.max_stack;
+  a.n_channels = ctx->n_channels;
+  a.n_sensors = ctx->max_sensor + 1;
+  a.src_kind = src->kind;
+  a.medium = src->medium;
+  a.n_photons = src->n_photons;
+  a.n_sources = src->n_sources;
+  a.positions = src->positions;
+  a.offsets = src->kind == XP_SRC_POINTS ? src->offsets : nullptr;
+  a.count_per_source = src->count_per_source;
+  a.per_source_events = src->kind == XP_SRC_POINTS ? src->per_source_events : 0;
+  a.chunk = lc.chunk;
+  a.dirs = src->directions;
+  a.pols = src->polarizations;
+  a.cyl_r = src->cyl_radius;
+  a.cyl_zlo = src->cyl_zlo;
+  a.cyl_zhi = src->cyl_zhi;
+  a.seed_lo = uint32_t(rp->seed);
+  a.seed_hi = uint32_t(rp->seed >> 32);
+  a.pid_base = rp->pid_base;
+  a.max_steps = rp->max_steps > 0 ? rp->max_steps : 10000;
+  a.eps = rp->eps;
+  a.grad_material = rp->grad_material;
+  a.surface_offset = rp->surface_offset;
+  for (size_t i = 0; i < ctx->mats.size(); ++i) {
+    a.mats[i].n = ctx->mats[i].n;
+    a.mats[i].abs_len = ctx->mats[i].abs_length;
+    a.mats[i].ray_len = ctx->mats[i].rayleigh_length;
+  }
+  for (size_t i = 0; i < ctx->surfs.size(); ++i) {
+    const xp_surface& s = ctx->surfs[i];
+    // cumulative thresholds of the partition, accumulated in double and rounded once
+    const double c1 = double(s.p_detect);
+    const double c2 = c1 + s.p_absorb;
+    const double c3 = c2 + s.r_diffuse;
+    const double c4 = c3 + s.r_specular;
+    a.surfs[i].c_detect = float(c1);
+    a.surfs[i].c_absorb = float(c2);
+    a.surfs[i].c_diffuse = float(c3);
+    a.surfs[i].c_specular = float(c4);
+    a.surfs[i].p_transmit = s.p_transmit;
+    const double rtot = double(s.r_diffuse) + s.r_specular;
+    a.surfs[i].inv_r = rtot > 0 ? float(1.0 / rtot) : 0.0f;
+    a.surfs[i].inv_t = s.p_transmit > 0 ? float(1.0 / double(s.p_transmit)) : 0.0f;
+    a.surfs[i].flags_grad = (s.flags & 0xff) | ((s.grad_param + 1) << 8);
+  }
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_depth, lc.block_size);
+  if (lds > ctx->max_lds)
+    return fail(ctx, XP_ERR_UNSUPPORTED, "LDS request of " + std::to_string(lds) +
+                                             " bytes exceeds the device limit; use fewer lds_levels "
+                                             "or a smaller block");
+  int per_cu = 0;
+  const hipError_t e = xp::max_blocks_per_cu(lc.block_size, lds, false, &per_cu);
+  if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+  if (per_cu <= 0) return fail(ctx, XP_ERR_UNSUPPORTED, "kernel does not fit on a CU");
+  if (lc.blocks_per_cu <= 0 || lc.blocks_per_cu > per_cu) lc.blocks_per_cu = per_cu;
+  grid = ctx->n_cu * lc.blocks_per_cu;
+  return XP_OK;
+}
+
+int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records, bool count,
+           const xp_launch_cfg& lc, int grid, hipStream_t s) {
+  if (a.n_photons == 0) return XP_OK;
+  unsigned long long* counter = ctx->d_counters + (ctx->ring_next++ % xp::kCounterRing);
+  a.work_counter = counter;
+  hipError_t e = xp::launch_reset(counter, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "launch(reset)");
+  e = xp::launch_propagate(a, mode, grad, records, count, lc.block_size, grid, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "launch(propagate)");
+  return XP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xp_version(void) { return "xephot 0.1 (gfx950)"; }
+
+const char* xp_last_error(const xp_context* ctx) {
+  return ctx ? ctx->err.c_str() : g_thread_err.c_str();
+}
+
+int xp_context_create(int hip_device, xp_context** out) {
+  try {
+    if (!out) return fail(nullptr, XP_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= n)
+      return fail(nullptr, XP_ERR_INVALID_ARG, "no such HIP device");
+    DeviceGuard g(hip_device);
+    if (g.status != hipSuccess) return hip_fail(nullptr, g.status, "hipSetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    xp_context* ctx = new xp_context();
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->max_lds = prop.sharedMemPerBlock;
+    e = hipMalloc(&ctx->d_counters, xp::kCounterRing * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+      delete ctx;
+      return hip_fail(nullptr, e, "hipMalloc(work counters)");
+    }
+    *out = ctx;
+    return XP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, XP_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(nullptr, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+void xp_context_destroy(xp_context* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  dfree(ctx->d_nodes);
+  dfree(ctx->d_tris);
+  dfree(ctx->d_channel);
+  dfree(ctx->d_counters);
+  delete ctx;
+}
+
+int xp_load_mesh(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                 const int32_t* mat_inner, const int32_t* mat_outer, const int32_t* surface,
+                 const int32_t* sensor) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  try {
+    if (!vtx || !tri || !mat_inner || !mat_outer || !surface || !sensor)
+      return fail(ctx, XP_ERR_INVALID_ARG, "null mesh array");
+    if (nv <= 0 || nt <= 0 || nt >= (int64_t(1) << 31) || nv >= (int64_t(1) << 31))
+      return fail(ctx, XP_ERR_INVALID_ARG, "nv and nt must be in [1, 2^31)");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+      if (!std::isfinite(vtx[i]))
+        return fail(ctx, XP_ERR_MESH, "non-finite vertex coordinate at vertex " + std::to_string(i / 3));
+    int32_t mm = -1, ms = -1, mse = -1;
+    for (int64_t t = 0; t < nt; ++t) {
+      const int32_t* q = tri + 3 * t;
+      for (int k = 0; k < 3; ++k)
+        if (q[k] < 0 || q[k] >= nv)
+          return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a vertex index out of range");
+      const float* p0 = vtx + 3 * int64_t(q[0]);
+      const float* p1 = vtx + 3 * int64_t(q[1]);
+      const float* p2 = vtx + 3 * int64_t(q[2]);
+      const double e1[3] = {double(p1[0]) - p0[0], double(p1[1]) - p0[1], double(p1[2]) - p0[2]};
+      const double e2[3] = {double(p2[0]) - p0[0], double(p2[1]) - p0[1], double(p2[2]) - p0[2]};
+      const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                   cz = e1[0] * e2[1] - e1[1] * e2[0];
+      if (0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) < 1e-12)
+        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " is degenerate (area < 1e-12 m^2)");
+      if (mat_inner[t] < 0 || mat_inner[t] > 255 || mat_outer[t] < 0 || mat_outer[t] > 255)
+        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a material id outside [0, 255]");
+      if (surface[t] < -1 || surface[t] > 65534)
+        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a surface id outside [-1, 65534]");
+      if (sensor[t] < -1)
+        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a sensor id < -1");
+      mm = std::max(mm, std::max(mat_inner[t], mat_outer[t]));
+      ms = std::max(ms, surface[t]);
+      mse = std::max(mse, sensor[t]);
+    }
+    ctx->vtx.assign(vtx, vtx + 3 * nv);
+    ctx->tri.assign(tri, tri + 3 * nt);
+    ctx->mat_in.assign(mat_inner, mat_inner + nt);
+    ctx->mat_out.assign(mat_outer, mat_outer + nt);
+    ctx->surf.assign(surface, surface + nt);
+    ctx->sensor.assign(sensor, sensor + nt);
+    ctx->max_mat = mm;
+    ctx->max_surf = ms;
+    ctx->max_sensor = mse;
+    ctx->mesh_loaded = true;
+    ctx->bvh_built = false;
+    ctx->tuned = false;
+    return XP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_set_materials(xp_context* ctx, const xp_material* m, int32_t n) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!m || n <= 0 || n > xp::kMaxMaterials)
+    return fail(ctx, XP_ERR_INVALID_ARG, "need 1..8 materials");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!finite_pos(m[i].n)) return fail(ctx, XP_ERR_INVALID_ARG, "refractive index must be finite and > 0");
+    if (!(m[i].abs_length > 0.0f) || !(m[i].rayleigh_length > 0.0f))
+      return fail(ctx, XP_ERR_INVALID_ARG, "lengths must be > 0 (INFINITY allowed)");
+  }
+  try {
+    ctx->mats.assign(m, m + n);
+  } catch (...) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  }
+  return XP_OK;
+}
+
+int xp_set_surfaces(xp_context* ctx, const xp_surface* s, int32_t n) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!s || n <= 0 || n > xp::kMaxSurfaces)
+    return fail(ctx, XP_ERR_INVALID_ARG, "need 1..16 surfaces");
+  for (int32_t i = 0; i < n; ++i) {
+    const float p[5] = {s[i].p_detect, s[i].p_absorb, s[i].r_diffuse, s[i].r_specular,
+                        s[i].p_transmit};
+    double sum = 0.0;
+    for (float x : p) {
+      if (!(x >= 0.0f && x <= 1.0f))
+        return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": probability outside [0, 1]");
+      sum += x;
+    }
+    if (std::fabs(sum - 1.0) > 1e-6)
+      return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": probabilities do not sum to 1");
+    if (s[i].grad_param != -1 && s[i].grad_param != 2 && s[i].grad_param != 3)
+      return fail(ctx, XP_ERR_INVALID_ARG, "grad_param must be -1, 2 or 3");
+    if (s[i].flags & ~XP_SURF_DETECT_FRONT_ONLY)
+      return fail(ctx, XP_ERR_INVALID_ARG, "unknown surface flag");
+  }
+  try {
+    ctx->surfs.assign(s, s + n);
+  } catch (...) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  }
+  return XP_OK;
+}
+
+int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_t n_sensors,
+                       int32_t n_channels) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!channel_of_sensor || n_sensors <= 0 || n_channels <= 0)
+    return fail(ctx, XP_ERR_INVALID_ARG, "need a map of n_sensors > 0 entries and n_channels > 0");
+  for (int32_t i = 0; i < n_sensors; ++i)
+    if (channel_of_sensor[i] < 0 || channel_of_sensor[i] >= n_channels)
+      return fail(ctx, XP_ERR_INVALID_ARG, "channel of sensor " + std::to_string(i) + " out of range");
+  try {
+    ctx->channel.assign(channel_of_sensor, channel_of_sensor + n_sensors);
+  } catch (...) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  }
+  ctx->n_channels = n_channels;
+  ctx->channel_set = true;
+  if (ctx->bvh_built) {
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    return upload_channel_map(ctx);
+  }
+  return XP_OK;
+}
+
+int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
+  const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
+  const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
+  if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
+    return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
+  if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
+    return fail(ctx, XP_ERR_STATE, "channel map does not cover the mesh's sensor ids");
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    xp::BvhResult r;
+    std::string err;
+    const int64_t nt = int64_t(ctx->mat_in.size());
+    if (!xp::build_bvh4(ctx->vtx.data(), ctx->tri.data(), nt, ctx->mat_in.data(),
+                        ctx->mat_out.data(), ctx->surf.data(), ctx->sensor.data(), leaf, bins, r, err))
+      return fail(ctx, XP_ERR_MESH, err);
+    if (r.max_stack > 512) return fail(ctx, XP_ERR_UNSUPPORTED, "BVH too deep");
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    ctx->bvh_built = false;
+    ctx->tuned = false;
+    dfree(ctx->d_nodes);
+    dfree(ctx->d_tris);
+    hipError_t e = hipMalloc(&ctx->d_nodes, r.nodes.size() * sizeof(xp::Node4));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(nodes)");
+    e = hipMalloc(&ctx->d_tris, r.tris.size() * sizeof(xp::TriRec));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(triangles)");
+    e = hipMemcpy(ctx->d_nodes, r.nodes.data(), r.nodes.size() * sizeof(xp::Node4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(nodes)");
+    e = hipMemcpy(ctx->d_tris, r.tris.data(), r.tris.size() * sizeof(xp::TriRec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(triangles)");
+    const int rc = upload_channel_map(ctx);
+    if (rc != XP_OK) return rc;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ctx->stats.n_nodes = int64_t(r.nodes.size());
+    ctx->stats.n_triangles = int64_t(r.tris.size());
+    ctx->stats.depth = r.depth;
+    ctx->stats.max_stack = r.max_stack;
+    ctx->stats.node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
+    ctx->stats.triangle_bytes = int64_t(r.tris.size() * sizeof(xp::TriRec));
+    ctx->stats.build_seconds = secs;
+    r.nodes.clear();
+    r.nodes.shrink_to_fit();
+    r.tris.clear();
+    r.tris.shrink_to_fit();
+    ctx->bvh = std::move(r);
+    ctx->bvh_built = true;
+    return XP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out) {
+  if (!ctx || !out) return fail(nullptr, XP_ERR_INVALID_ARG, "null argument");
+  if (!ctx->bvh_built) return fail(const_cast<xp_context*>(ctx), XP_ERR_STATE, "no BVH");
+  *out = ctx->stats;
+  return XP_OK;
+}
+
+int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp, int32_t* d_hit_map,
+                 double* d_grad, xp_photon_record* d_records, uint64_t* d_stats,
+                 const xp_launch_cfg* lc, xp_stream stream) {
+  try {
+    xp::LaunchArgs a;
+    xp_launch_cfg cfg;
+    int grid = 0;
+    if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    int rc = prepare(ctx, src, rp, lc, a, cfg, grid);
+    if (rc != XP_OK) return rc;
+    a.hit_map = d_hit_map;
+    a.grad = d_grad;
+    a.records = d_records;
+    a.stats = reinterpret_cast<unsigned long long*>(d_stats);
+    return launch(ctx, a, xp::kForward, d_grad != nullptr, d_records != nullptr, d_stats != nullptr,
+                  cfg, grid, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                const float* d_grad_hits, double* d_grad_params, const xp_launch_cfg* lc,
+                xp_stream stream) {
+  try {
+    xp::LaunchArgs a;
+    xp_launch_cfg cfg;
+    int grid = 0;
+    if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+    if (!d_grad_hits || !d_grad_params)
+      return fail(ctx, XP_ERR_INVALID_ARG, "null gradient buffer");
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    int rc = prepare(ctx, src, rp, lc, a, cfg, grid);
+    if (rc != XP_OK) return rc;
+    a.grad_hits = d_grad_hits;
+    a.grad_params = d_grad_params;
+    return launch(ctx, a, xp::kBackward, false, false, false, cfg, grid,
+                  static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                int64_t sample_photons, xp_launch_cfg* out, xp_stream stream) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!src || !rp || sample_photons <= 0) return fail(ctx, XP_ERR_INVALID_ARG, "bad arguments");
+  try {
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    xp_sources sample = *src;
+    sample.n_photons = std::min(src->n_photons, sample_photons);
+    const int64_t n_events =
+        (src->kind == XP_SRC_POINTS && src->per_source_events) ? src->n_sources : 1;
+    int32_t* d_map = nullptr;
+    const size_t map_bytes = size_t(n_events) * std::max(ctx->n_channels, 1) * sizeof(int32_t);
+    hipError_t e = hipMalloc(&d_map, map_bytes);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(autotune map)");
+    hipEvent_t t0, t1;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    float best_ms = 1e30f;
+    xp_launch_cfg best = default_cfg();
+    int rc = XP_OK;
+    const int blocks[3] = {64, 128, 256};
+    const int levels[3] = {0, 2, 3};
+    const int chunks[2] = {64, 256};
+    for (int b : blocks)
+      for (int l : levels)
+        for (int c : chunks) {
+          xp_launch_cfg cand{b, 0, c, l};
+          xp::LaunchArgs a;
+          xp_launch_cfg cfg;
+          int grid = 0;
+          rc = prepare(ctx, &sample, rp, &cand, a, cfg, grid);
+          if (rc == XP_ERR_UNSUPPORTED) {
+            rc = XP_OK;
+            continue;
+          }
+          if (rc != XP_OK) break;
+          a.hit_map = d_map;
+          float ms_best = 1e30f;
+          for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(t0, s);
+            rc = launch(ctx, a, xp::kForward, false, false, false, cfg, grid, s);
+            if (rc != XP_OK) break;
+            (void)hipEventRecord(t1, s);
+            e = hipEventSynchronize(t1);
+            if (e != hipSuccess) {
+              rc = hip_fail(ctx, e, "autotune run");
+              break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            ms_best = std::min(ms_best, ms);
+          }
+          if (rc != XP_OK) break;
+          if (ms_best < best_ms) {
+            best_ms = ms_best;
+            best = cfg;
+          }
+        }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipFree(d_map);
+    if (rc != XP_OK) return rc;
+    best.blocks_per_cu = 0;  // re-derived from occupancy at launch
+    ctx->tuned_cfg = best;
+    ctx->tuned = true;
+    if (out) *out = best;
+    return XP_OK;
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* dir,
+                   const int32_t* skip, float tmin, float tmax, int32_t brute, int32_t* out_tri,
+                   float* out_t, xp_stream stream) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!ctx->bvh_built) return fail(ctx, XP_ERR_STATE, "no BVH");
+  if (n < 0 || (n > 0 && (!orig || !dir || !out_tri || !out_t)))
+    return fail(ctx, XP_ERR_INVALID_ARG, "bad ray arrays");
+  if (n >= (int64_t(1) << 37)) return fail(ctx, XP_ERR_INVALID_ARG, "too many rays");
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const hipError_t e = xp::launch_closest_hit(
+      ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_triangles), ctx->bvh.max_stack, n, orig, dir,
+      skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "launch(closest_hit)");
+  return XP_OK;
+}
+
+int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
+              const float* in_pol, float cyl_radius, float cyl_zlo, float cyl_zhi, float* out_dir,
+              float* out_pol, xp_stream stream) {
+  if (kind < 0 || kind > 3 || n < 0) return fail(nullptr, XP_ERR_INVALID_ARG, "bad sampler request");
+  if (n > 0 && (!out_dir || !out_pol)) return fail(nullptr, XP_ERR_INVALID_ARG, "null output");
+  if (n > 0 && (kind == 1 || kind == 2) && !in_dir) return fail(nullptr, XP_ERR_INVALID_ARG, "null input");
+  if (n > 0 && kind == 2 && !in_pol) return fail(nullptr, XP_ERR_INVALID_ARG, "null input");
+  if (n >= (int64_t(1) << 37)) return fail(nullptr, XP_ERR_INVALID_ARG, "too many samples");
+  const hipError_t e = xp::launch_sample(kind, seed, pid0, n, in_dir, in_pol, cyl_radius, cyl_zlo,
+                                         cyl_zhi, out_dir, out_pol, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(sample)");
+  return XP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,802 @@
+// propagate.hip -- gfx950 kernels of the optical-photon transport.
+//
+// One lane carries one photon.  A workgroup stages the top levels of the
+// 4-wide BVH in LDS, then loops persistently: lanes whose photon has ended
+// are refilled from a per-wave pool of photon ids (one wave ballot, one
+// atomic per `chunk` photons), and every live lane advances its photon by one
+// step: free paths for absorption and Rayleigh scattering, closest hit along
+// the ray, then the bulk or surface interaction.  Photon i's random numbers
+// come from Philox-4x32-10 keyed by the seed with the photon id in the
+// counter, so results do not depend on which lane or wave runs the photon.
+//
+// The processes follow the paper's optical model (section "Optical
+// properties", table tab:optical): absorption and Rayleigh scattering with
+// exponential free paths; Rayleigh scattering with the dipole law (appendix
+// item 3); explicit angle-independent surfaces (detect / absorb / diffuse /
+// specular / transmit); Fresnel reflection and refraction with total internal
+// reflection at dielectric boundaries (quartz, LXe, GXe); detection at sensors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "xp_internal.h"
+
+namespace xp {
+namespace {
+
+constexpr float kInfF = __builtin_huge_valf();
+constexpr float kCns = 0.299792458f;  // m/ns
+
+// ---------------------------------------------------------------------------
+// random numbers: Philox-4x32-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+struct R4 { float u0, u1, u2, u3; };
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// (2k + 1) / 2^24 from the top 23 bits: exact in FP32, strictly inside (0, 1)
+__device__ __forceinline__ float u01(uint32_t x) {
+  return (float(x >> 9) + 0.5f) * 1.1920928955078125e-7f;
+}
+
+__device__ __forceinline__ R4 draw(uint32_t seed_lo, uint32_t seed_hi, uint64_t pid, uint32_t step,
+                                   uint32_t sub) {
+  const uint4 r = philox(uint32_t(pid), uint32_t(pid >> 32), step, sub, seed_lo, seed_hi);
+  return R4{u01(r.x), u01(r.y), u01(r.z), u01(r.w)};
+}
+
+// ---------------------------------------------------------------------------
+// small vector algebra
+// ---------------------------------------------------------------------------
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
+__device__ __forceinline__ bool finite3(f3 a) {
+  return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+}
+__device__ __forceinline__ float comp(f3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// orthonormal basis of a unit vector (Duff et al., JCGT 2017) with the branch
+// switched at n_z = -1/2: for normals in the xy plane (detector walls) the sign
+// of n_z is rounding noise and must not select the basis
+__device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
+  const float s = n.z >= -0.5f ? 1.0f : -1.0f;
+  const float a = -1.0f / (s + n.z);
+  const float b = n.x * n.y * a;
+  b1 = {1.0f + s * n.x * n.x * a, s * b, -s * n.x};
+  b2 = {b, s + n.y * n.y * a, -n.y};
+}
+
+__device__ __forceinline__ f3 isotropic(float u0, float u1) {
+  const float c = 1.0f - 2.0f * u0;
+  const float s = sqrtf(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
+  float sp, cp;
+  sincospif(2.0f * u1, &sp, &cp);
+  return {s * cp, s * sp, c};
+}
+
+__device__ __forceinline__ f3 random_polarization(f3 d, float u) {
+  f3 b1, b2;
+  onb(d, b1, b2);
+  float sp, cp;
+  sincospif(2.0f * u, &sp, &cp);
+  return cp * b1 + sp * b2;
+}
+
+// ---------------------------------------------------------------------------
+// photon state
+// ---------------------------------------------------------------------------
+struct Photon {
+  f3 pos, dir, pol;
+  float time;
+  int32_t medium, last_tri, steps, flag, event, sensor;
+  float path_len;   // in the gradient material
+  int32_t n_sca;    // Rayleigh scatters in the gradient material
+  float sum_inv_r, sum_inv_t;
+};
+
+enum : int32_t {
+  F_DETECT = 1, F_SENSOR_ABSORB = 2, F_SURFACE_ABSORB = 3, F_BULK_ABSORB = 4, F_ESCAPED = 5,
+  F_MAX_STEPS = 6, F_NAN_ABORT = 7, F_GEOM = 0x100
+};
+
+// dipole Rayleigh scattering: isotropic trial k', keep with probability
+// 1 - (e.k')^2; new polarization = e projected off k' (trial 64 kept if all fail)
+__device__ __forceinline__ void rayleigh(Photon& p, uint32_t s0, uint32_t s1, uint64_t pid,
+                                         uint32_t step) {
+  f3 k{0.f, 0.f, 1.f}, e{1.f, 0.f, 0.f};
+  for (uint32_t j = 0; j < 64; ++j) {
+    const R4 r = draw(s0, s1, pid, step, 2u + j);
+    k = isotropic(r.u0, r.u1);
+    const float ek = dot(p.pol, k);
+    e = p.pol - ek * k;
+    if (r.u2 < 1.0f - ek * ek) break;
+  }
+  p.dir = k;
+  p.pol = normalize(e);
+}
+
+// Lambertian reflection into the hemisphere of n_out, fresh polarization
+__device__ __forceinline__ void lambertian(Photon& p, f3 n_out, const R4& r) {
+  f3 b1, b2;
+  onb(n_out, b1, b2);
+  const float ct = sqrtf(r.u0);
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - r.u0));
+  float sp, cp;
+  sincospif(2.0f * r.u1, &sp, &cp);
+  p.dir = normalize((st * cp) * b1 + (st * sp) * b2 + ct * n_out);
+  p.pol = random_polarization(p.dir, r.u2);
+}
+
+// mirror reflection about the plane of unit normal n (defined at normal incidence)
+__device__ __forceinline__ void specular(Photon& p, f3 n) {
+  p.dir = normalize(p.dir - (2.0f * dot(p.dir, n)) * n);
+  p.pol = normalize(p.pol - (2.0f * dot(p.pol, n)) * n);
+}
+
+// Fresnel at a real-index boundary; nhat points back into the incident medium.
+// Returns true if transmitted.
+__device__ __forceinline__ bool fresnel(Photon& p, f3 nhat, float n1, float n2, float u) {
+  const f3 d = p.dir, e = p.pol;
+  const float ci = -dot(d, nhat);
+  const float eta = n1 / n2;
+  const float st2 = eta * eta * (1.0f - ci * ci);
+  if (st2 >= 1.0f) {
+    specular(p, nhat);
+    return false;
+  }
+  const float ct = sqrtf(1.0f - st2);
+  const float rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
+  const float rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
+  const float ts = 2.0f * n1 * ci / (n1 * ci + n2 * ct);
+  const float tp = 2.0f * n1 * ci / (n2 * ci + n1 * ct);
+  const f3 sv = cross(d, nhat);
+  const float sl = sqrtf(dot(sv, sv));
+  const f3 s = (sl < 1e-6f) ? e : (1.0f / sl) * sv;
+  const float as = dot(e, s);
+  const float ap = dot(e, cross(s, d));
+  const float R = as * as * rs * rs + ap * ap * rp * rp;
+  if (u < R) {
+    const f3 dr = normalize(d + (2.0f * ci) * nhat);
+    p.pol = normalize((rs * as) * s + (rp * ap) * cross(s, dr));
+    p.dir = dr;
+    return false;
+  }
+  const f3 dt = normalize(eta * d + (eta * ci - ct) * nhat);
+  p.pol = normalize((ts * as) * s + (tp * ap) * cross(s, dt));
+  p.dir = dt;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// ray / triangle (watertight, Woop, Benthin and Wald, JCGT 2013), FP32
+// ---------------------------------------------------------------------------
+struct RayW {
+  f3 o;
+  int kx, ky, kz;
+  float sx, sy, sz;
+};
+
+__device__ __forceinline__ RayW make_ray(f3 o, f3 d) {
+  RayW r;
+  r.o = o;
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  r.kx = r.kz == 2 ? 0 : r.kz + 1;
+  r.ky = r.kx == 2 ? 0 : r.kx + 1;
+  const float dz = comp(d, r.kz);
+  if (dz < 0.0f) {
+    const int t = r.kx;
+    r.kx = r.ky;
+    r.ky = t;
+  }
+  r.sx = comp(d, r.kx) / dz;
+  r.sy = comp(d, r.ky) / dz;
+  r.sz = 1.0f / dz;
+  return r;
+}
+
+// hit distance or +inf; products are never contracted so that the edge
+// function of a shared edge is exactly negated between its two triangles
+__device__ __forceinline__ float intersect(const RayW& r, const float* va, const float* vb,
+                                           const float* vc) {
+  const f3 a{va[0] - r.o.x, va[1] - r.o.y, va[2] - r.o.z};
+  const f3 b{vb[0] - r.o.x, vb[1] - r.o.y, vb[2] - r.o.z};
+  const f3 c{vc[0] - r.o.x, vc[1] - r.o.y, vc[2] - r.o.z};
+  const float akz = comp(a, r.kz), bkz = comp(b, r.kz), ckz = comp(c, r.kz);
+  const float ax = fmaf(-r.sx, akz, comp(a, r.kx)), ay = fmaf(-r.sy, akz, comp(a, r.ky));
+  const float bx = fmaf(-r.sx, bkz, comp(b, r.kx)), by = fmaf(-r.sy, bkz, comp(b, r.ky));
+  const float cx = fmaf(-r.sx, ckz, comp(c, r.kx)), cy = fmaf(-r.sy, ckz, comp(c, r.ky));
+  const float u = __fsub_rn(__fmul_rn(cx, by), __fmul_rn(cy, bx));
+  const float v = __fsub_rn(__fmul_rn(ax, cy), __fmul_rn(ay, cx));
+  const float w = __fsub_rn(__fmul_rn(bx, ay), __fmul_rn(by, ax));
+  if ((u < 0.0f || v < 0.0f || w < 0.0f) && (u > 0.0f || v > 0.0f || w > 0.0f)) return kInfF;
+  const float det = __fadd_rn(__fadd_rn(u, v), w);
+  if (det == 0.0f) return kInfF;
+  const float az = r.sz * akz, bz = r.sz * bkz, cz = r.sz * ckz;
+  const float t = __fadd_rn(__fadd_rn(__fmul_rn(u, az), __fmul_rn(v, bz)), __fmul_rn(w, cz));
+  return __fdiv_rn(t, det);
+}
+
+struct Best {
+  float t;
+  int32_t tri;   // mesh triangle index (-1: none)
+  int32_t rec;   // record index
+};
+
+__device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, int32_t k,
+                                              const RayW& r, float tmin, int32_t skip, Best& b) {
+  const float4 A = *reinterpret_cast<const float4*>(tris[k].a);
+  const float4 B = *reinterpret_cast<const float4*>(tris[k].b);
+  const float4 C = *reinterpret_cast<const float4*>(tris[k].c);
+  const int32_t id = __float_as_int(A.w);
+  if (id == skip) return;
+  const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
+  const float t = intersect(r, va, vb, vc);
+  if (!(t > tmin) || !(t <= b.t) || !(t < kInfF)) return;
+  if (t < b.t || b.tri < 0 || id < b.tri) {
+    b.t = t;
+    b.tri = id;
+    b.rec = k;
+  }
+}
+
+struct Counters {
+  uint32_t nodes, tris;
+};
+
+// BVH closest hit: t in (tmin, b.t], ties to the lower triangle index.
+template <bool kCount>
+__device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
+                                         int32_t n_lds, const TriRec* __restrict__ tris,
+                                         int32_t* stack, int32_t stride, int32_t depth_cap, f3 o,
+                                         f3 d, float tmin, int32_t skip, Best& b, Counters& cnt) {
+  const RayW ray = make_ray(o, d);
+  const float tiny = 1e-30f;
+  const f3 inv{1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
+               1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
+               1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z))};
+  const f3 oi{o.x * inv.x, o.y * inv.y, o.z * inv.z};
+  int32_t node = 0;
+  int32_t sp = 0;
+  while (true) {
+    float4 q[8];
+    if (node < n_lds) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) q[i] = lds_nodes[node * 8 + i];
+    } else {
+      const float4* g = reinterpret_cast<const float4*>(gnodes + node);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) q[i] = g[i];
+    }
+    if (kCount) cnt.nodes++;
+    const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+    const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
+    const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
+    const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
+    const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
+    const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
+    const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
+                              __float_as_int(q[6].z), __float_as_int(q[6].w)};
+    const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
+                              __float_as_int(q[7].z), __float_as_int(q[7].w)};
+    int32_t next = -1;
+    float next_t = kInfF;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (count[i] < 0) continue;
+      const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
+      const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
+      const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
+      const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+      const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b.t));
+      if (!(tn <= tf * 1.0000005f)) continue;
+      if (count[i] > 0) {
+        const int32_t first = ~child[i];
+        for (int32_t k = first; k < first + count[i]; ++k) {
+          if (kCount) cnt.tris++;
+          test_triangle(tris, k, ray, tmin, skip, b);
+        }
+      } else if (tn < next_t) {
+        if (next >= 0) {
+          if (sp >= depth_cap) return false;
+          stack[sp++ * stride] = next;
+        }
+        next = child[i];
+        next_t = tn;
+      } else {
+        if (sp >= depth_cap) return false;
+        stack[sp++ * stride] = child[i];
+      }
+    }
+    if (next >= 0) {
+      node = next;
+    } else {
+      if (sp == 0) break;
+      node = stack[--sp * stride];
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// sources
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t source_of(const LaunchArgs& a, int64_t i) {
+  if (a.offsets == nullptr) return i / a.count_per_source;
+  int64_t lo = 0, hi = a.n_sources;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a.offsets[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
+  p.time = 0.0f;
+  p.medium = a.medium;
+  p.last_tri = -1;
+  p.steps = 0;
+  p.flag = 0;
+  p.event = 0;
+  p.sensor = -1;
+  p.path_len = 0.0f;
+  p.n_sca = 0;
+  p.sum_inv_r = 0.0f;
+  p.sum_inv_t = 0.0f;
+  if (a.src_kind == XP_SRC_EXPLICIT) {
+    p.pos = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
+    p.dir = normalize(f3{a.dirs[3 * i], a.dirs[3 * i + 1], a.dirs[3 * i + 2]});
+    const f3 e{a.pols[3 * i], a.pols[3 * i + 1], a.pols[3 * i + 2]};
+    p.pol = normalize(e - dot(e, p.dir) * p.dir);
+    return;
+  }
+  const R4 r = draw(a.seed_lo, a.seed_hi, pid, 0u, 0u);
+  p.dir = isotropic(r.u0, r.u1);
+  p.pol = random_polarization(p.dir, r.u2);
+  if (a.src_kind == XP_SRC_POINTS) {
+    const int64_t s = source_of(a, i);
+    p.pos = {a.positions[3 * s], a.positions[3 * s + 1], a.positions[3 * s + 2]};
+    p.event = a.per_source_events ? int32_t(s) : 0;
+  } else {
+    const R4 q = draw(a.seed_lo, a.seed_hi, pid, 0u, 1u);
+    const float rr = a.cyl_r * sqrtf(q.u0);
+    float sp, cp;
+    sincospif(2.0f * q.u1, &sp, &cp);
+    p.pos = {rr * cp, rr * sp, a.cyl_zlo + (a.cyl_zhi - a.cyl_zlo) * q.u2};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one transport step; returns true when the photon has ended
+// ---------------------------------------------------------------------------
+template <bool kGradAcc, bool kCount>
+__device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint64_t pid,
+                                            const float4* lds_nodes, int32_t* stack,
+                                            int32_t stride, Counters& cnt) {
+  const int32_t step = ++p.steps;
+  const DevMaterial m = a.mats[p.medium];
+  const R4 r = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 0u);
+  const float d_abs = isinf(m.abs_len) ? kInfF : -m.abs_len * logf(r.u0);
+  const float d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
+  const float d_bulk = fminf(d_abs, d_sca);
+  Best b{d_bulk, -1, -1};
+  if (!traverse<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, a.tris, stack, stride, a.stack_depth,
+                        p.pos, p.dir, a.eps, p.last_tri, b, cnt)) {
+    p.flag |= F_NAN_ABORT;  // traversal stack exhausted (prevented by the host's sizing)
+    return true;
+  }
+  const bool in_grad = p.medium == a.grad_material;
+  if (b.tri < 0) {
+    if (isinf(d_bulk)) {
+      p.flag |= F_ESCAPED;
+      return true;
+    }
+    p.pos = p.pos + d_bulk * p.dir;
+    p.time += d_bulk * m.n / kCns;
+    if (kGradAcc && in_grad) p.path_len += d_bulk;
+    if (d_abs <= d_sca) {
+      p.flag |= F_BULK_ABSORB;
+      return true;
+    }
+    if (kGradAcc && in_grad) p.n_sca += 1;
+    rayleigh(p, a.seed_lo, a.seed_hi, pid, uint32_t(step));
+    p.last_tri = -1;
+  } else {
+    const int32_t k = b.tri;
+    p.pos = p.pos + b.t * p.dir;
+    p.time += b.t * m.n / kCns;
+    if (kGradAcc && in_grad) p.path_len += b.t;
+    const float4 A = *reinterpret_cast<const float4*>(a.tris[b.rec].a);
+    const float4 B = *reinterpret_cast<const float4*>(a.tris[b.rec].b);
+    const float4 C = *reinterpret_cast<const float4*>(a.tris[b.rec].c);
+    const f3 v0{A.x, A.y, A.z};
+    const f3 N = normalize(cross(f3{B.x, B.y, B.z} - v0, f3{C.x, C.y, C.z} - v0));
+    const uint32_t packed = __float_as_uint(B.w);
+    const int32_t sensor = __float_as_int(C.w);
+    const int32_t mat_in = int32_t(packed & 0xffu), mat_out = int32_t((packed >> 8) & 0xffu);
+    const int32_t si = int32_t(packed >> 16) - 1;
+    const bool from_outer = dot(p.dir, N) < 0.0f;
+    const int32_t m_from = from_outer ? mat_out : mat_in;
+    const int32_t m_to = from_outer ? mat_in : mat_out;
+    if (m_from != p.medium) {
+      p.flag |= F_GEOM;
+      p.medium = m_from;
+    }
+    const f3 n_back = from_outer ? N : (-1.0f) * N;
+    p.last_tri = k;
+    if (si >= 0) {
+      const DevSurface s = a.surfs[si];
+      const int32_t sflags = s.flags_grad & 0xff;
+      const int32_t gpar = (s.flags_grad >> 8) - 1;
+      const bool is_sensor = sensor >= 0;
+      if ((sflags & XP_SURF_DETECT_FRONT_ONLY) && !from_outer) {
+        p.flag |= F_SURFACE_ABSORB;
+        return true;
+      }
+      const float u = r.u2;
+      if (u < s.c_detect) {
+        if (is_sensor) {
+          p.flag |= F_DETECT;
+          p.sensor = sensor;
+        } else {
+          p.flag |= F_SURFACE_ABSORB;
+        }
+        return true;
+      }
+      if (u < s.c_absorb) {
+        if (is_sensor) {
+          p.flag |= F_SENSOR_ABSORB;
+          p.sensor = sensor;
+        } else {
+          p.flag |= F_SURFACE_ABSORB;
+        }
+        return true;
+      }
+      bool through = false;
+      if (u < s.c_diffuse) {
+        lambertian(p, n_back, draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 1u));
+        if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
+      } else if (u < s.c_specular) {
+        specular(p, N);
+        if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
+      } else if (s.p_transmit > 0.0f) {
+        p.medium = m_to;
+        through = true;
+        if (kGradAcc && gpar == 3) p.sum_inv_t += s.inv_t;
+      } else {
+        p.flag |= is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB;
+        if (is_sensor) p.sensor = sensor;
+        return true;
+      }
+      p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
+    } else {
+      const float n1 = a.mats[m_from].n, n2 = a.mats[m_to].n;
+      bool through = true;
+      if (n1 != n2) through = fresnel(p, n_back, n1, n2, r.u2);
+      if (through) p.medium = m_to;
+      p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
+    }
+  }
+  if (!finite3(p.pos) || !finite3(p.dir) || !finite3(p.pol)) {
+    p.flag |= F_NAN_ABORT;
+    return true;
+  }
+  if (step >= a.max_steps) {
+    p.flag |= F_MAX_STEPS;
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(x >> 32));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// the persistent transport kernel
+//   kMode: kForward (hit map, optional gradient tallies) or kBackward (replay)
+// ---------------------------------------------------------------------------
+template <int kMode, bool kGrad, bool kRecords, bool kCount>
+__global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
+  extern __shared__ float4 lds[];
+  constexpr bool kGradAcc = kGrad || kMode == kBackward;
+  float4* lds_nodes = lds;
+  int32_t* stack_base = reinterpret_cast<int32_t*>(lds + a.n_lds_nodes * 8);
+  unsigned long long* blk_stats =
+      reinterpret_cast<unsigned long long*>(stack_base + a.stack_depth * blockDim.x);
+  const float4* gn = reinterpret_cast<const float4*>(a.nodes);
+  for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
+  if (kCount)
+    for (int32_t i = threadIdx.x; i < kStatsWords; i += blockDim.x) blk_stats[i] = 0ull;
+  __syncthreads();
+  int32_t* stack = stack_base + threadIdx.x;
+  const int32_t stride = blockDim.x;
+  const uint32_t lane = lane_rank(~0ull);
+
+  Photon p;
+  bool alive = false;
+  int64_t idx = 0;
+  uint64_t pid = 0;
+  uint64_t pool_next = 0, pool_end = 0;
+  bool exhausted = false;
+  Counters cnt{0u, 0u};
+  uint32_t n_steps = 0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+  while (true) {
+    // ---- refill lanes whose photon has ended (wave-uniform control flow) ----
+    uint64_t dead = __ballot(!alive);
+    while (dead != 0ull && !exhausted) {
+      if (pool_next >= pool_end) {
+        uint64_t base = 0;
+        if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
+        base = bcast64(base);
+        if (base >= uint64_t(a.n_photons)) {
+          exhausted = true;
+          break;
+        }
+        pool_next = base;
+        pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
+      }
+      const uint64_t avail = pool_end - pool_next;
+      const uint32_t rank = lane_rank(dead);
+      if (!alive && rank < avail) {
+        idx = int64_t(pool_next + rank);
+        pid = a.pid_base + uint64_t(idx);
+        emit(p, a, idx, pid);
+        alive = true;
+      }
+      const uint64_t ndead = uint64_t(__popcll(dead));
+      pool_next += ndead < avail ? ndead : avail;
+      dead = __ballot(!alive);
+    }
+    if (__ballot(alive) == 0ull) break;
+    if (!alive) continue;
+
+    // ---- one step of the live photon ----
+    const bool ended = step_photon<kGradAcc, kCount>(p, a, pid, lds_nodes, stack, stride, cnt);
+    if (kCount) n_steps++;
+    if (!ended) continue;
+    alive = false;
+    const int32_t fl = p.flag & 0xff;
+    if (fl == F_DETECT) {
+      const int64_t cell = int64_t(p.event) * a.n_channels + a.channel_of_sensor[p.sensor];
+      float sc[4] = {0.f, 0.f, 0.f, 0.f};
+      if (kGradAcc) {
+        if (a.grad_material >= 0) {
+          const DevMaterial gm = a.mats[a.grad_material];
+          const float s0 = p.path_len / (gm.abs_len * gm.abs_len);
+          const float s1 = p.path_len / (gm.ray_len * gm.ray_len) - float(p.n_sca) / gm.ray_len;
+          sc[0] = isfinite(s0) ? s0 : 0.0f;
+          sc[1] = isfinite(s1) ? s1 : 0.0f;
+        }
+        sc[2] = p.sum_inv_r;
+        sc[3] = p.sum_inv_t;
+      }
+      if (kMode == kForward) {
+        if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
+        if (kGrad && a.grad) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, double(sc[q]));
+        }
+      } else {
+        const double w = double(a.grad_hits[cell]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += w * double(sc[q]);
+      }
+    }
+    if (kRecords) {
+      xp_photon_record& rec = a.records[idx];
+      rec.flag = p.flag; rec.last_tri = p.last_tri; rec.sensor = p.sensor; rec.steps = p.steps;
+      rec.event = p.event; rec.medium = p.medium; rec.n_scatter = p.n_sca; rec.reserved = 0;
+      rec.pos[0] = p.pos.x; rec.pos[1] = p.pos.y; rec.pos[2] = p.pos.z; rec.time = p.time;
+      rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z; rec.path_len = p.path_len;
+      rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z; rec.sum_inv_r = p.sum_inv_r;
+      rec.sum_inv_t = p.sum_inv_t; rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
+    }
+    if (kCount) {
+      atomicAdd(&blk_stats[fl], 1ull);
+      if (p.flag & F_GEOM) atomicAdd(&blk_stats[8], 1ull);
+    }
+  }
+
+  // ---- per-wave reductions at exit ----
+  if (kMode == kBackward) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double s = wave_sum(acc[q]);
+      if (lane == 0 && s != 0.0) atomicAdd(a.grad_params + q, s);
+    }
+  }
+  if (kCount) {
+    const unsigned long long s9 = wave_sum_u64(n_steps);
+    const unsigned long long s10 = wave_sum_u64(cnt.nodes);
+    const unsigned long long s11 = wave_sum_u64(cnt.tris);
+    if (lane == 0) {
+      atomicAdd(&blk_stats[9], s9);
+      atomicAdd(&blk_stats[10], s10);
+      atomicAdd(&blk_stats[11], s11);
+    }
+    __syncthreads();
+    if (threadIdx.x < 12 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
+  }
+}
+
+__global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
+
+// closest hit for a batch of rays (test hook)
+__global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, const TriRec* tris,
+                                                         int32_t n_tris, int32_t stack_depth,
+                                                         int64_t n, const float* orig,
+                                                         const float* dir, const int32_t* skip,
+                                                         float tmin, float tmax, int32_t brute,
+                                                         int32_t* out_tri, float* out_t) {
+  extern __shared__ float4 lds[];
+  int32_t* stack = reinterpret_cast<int32_t*>(lds) + threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const f3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
+  const f3 d{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+  const int32_t sk = skip ? skip[i] : -1;
+  Best b{tmax, -1, -1};
+  Counters c{0u, 0u};
+  bool ok = true;
+  if (brute) {
+    const RayW r = make_ray(o, d);
+    for (int32_t k = 0; k < n_tris; ++k) test_triangle(tris, k, r, tmin, sk, b);
+  } else {
+    // no node is staged (n_lds = 0); the LDS base is passed rather than a null
+    // pointer, which this toolchain's inliner fails on
+    ok = traverse<false>(nodes, lds, 0, tris, stack, blockDim.x, stack_depth, o, d, tmin, sk, b,
+                         c);
+  }
+  out_tri[i] = ok ? b.tri : -2;
+  out_t[i] = b.tri >= 0 ? b.t : kInfF;
+}
+
+// samplers with the transport's random-number schedule (test hook)
+__global__ void sample_kernel(int32_t kind, uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n,
+                              const float* in_dir, const float* in_pol, float cyl_r, float zlo,
+                              float zhi, float* out_dir, float* out_pol) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t pid = pid0 + uint64_t(i);
+  Photon p;
+  p.pos = p.dir = p.pol = f3{0.f, 0.f, 0.f};
+  if (kind == 0) {
+    const R4 r = draw(s0, s1, pid, 0u, 0u);
+    p.dir = isotropic(r.u0, r.u1);
+    p.pol = random_polarization(p.dir, r.u2);
+  } else if (kind == 1) {
+    lambertian(p, f3{in_dir[3 * i], in_dir[3 * i + 1], in_dir[3 * i + 2]}, draw(s0, s1, pid, 1u, 1u));
+  } else if (kind == 2) {
+    p.dir = f3{in_dir[3 * i], in_dir[3 * i + 1], in_dir[3 * i + 2]};
+    p.pol = f3{in_pol[3 * i], in_pol[3 * i + 1], in_pol[3 * i + 2]};
+    rayleigh(p, s0, s1, pid, 1u);
+  } else {
+    const R4 q = draw(s0, s1, pid, 0u, 1u);
+    const float rr = cyl_r * sqrtf(q.u0);
+    float sp, cp;
+    sincospif(2.0f * q.u1, &sp, &cp);
+    p.dir = {rr * cp, rr * sp, zlo + (zhi - zlo) * q.u2};
+  }
+  out_dir[3 * i] = p.dir.x; out_dir[3 * i + 1] = p.dir.y; out_dir[3 * i + 2] = p.dir.z;
+  out_pol[3 * i] = p.pol.x; out_pol[3 * i + 1] = p.pol.y; out_pol[3 * i + 2] = p.pol.z;
+}
+
+template <int kMode, bool kGrad, bool kRecords, bool kCount>
+hipError_t launch_one(const LaunchArgs& a, int block, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((propagate_kernel<kMode, kGrad, kRecords, kCount>), dim3(grid), dim3(block),
+                     lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_depth, int block) {
+  return size_t(n_lds_nodes) * sizeof(Node4) + size_t(stack_depth) * block * 4 +
+         kStatsWords * sizeof(unsigned long long);
+}
+
+hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
+                            int block, int grid, hipStream_t s) {
+  const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_depth, block);
+  if (mode == kBackward) {
+    if (records || count || grad) return hipErrorInvalidValue;
+    return launch_one<kBackward, false, false, false>(a, block, grid, lds, s);
+  }
+  const int key = (grad ? 4 : 0) | (records ? 2 : 0) | (count ? 1 : 0);
+  switch (key) {
+    case 0: return launch_one<kForward, false, false, false>(a, block, grid, lds, s);
+    case 1: return launch_one<kForward, false, false, true>(a, block, grid, lds, s);
+    case 2: return launch_one<kForward, false, true, false>(a, block, grid, lds, s);
+    case 3: return launch_one<kForward, false, true, true>(a, block, grid, lds, s);
+    case 4: return launch_one<kForward, true, false, false>(a, block, grid, lds, s);
+    case 5: return launch_one<kForward, true, false, true>(a, block, grid, lds, s);
+    case 6: return launch_one<kForward, true, true, false>(a, block, grid, lds, s);
+    default: return launch_one<kForward, true, true, true>(a, block, grid, lds, s);
+  }
+}
+
+hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, int* out) {
+  if (count)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, reinterpret_cast<const void*>(propagate_kernel<kForward, true, true, true>), block,
+        lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      out, reinterpret_cast<const void*>(propagate_kernel<kForward, false, false, false>), block,
+      lds_bytes);
+}
+
+hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_tris,
+                              int32_t stack_depth, int64_t n, const float* orig, const float* dir,
+                              const int32_t* skip, float tmin, float tmax, int32_t brute,
+                              int32_t* out_tri, float* out_t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int block = 64;
+  const int64_t grid = (n + block - 1) / block;
+  const size_t lds = size_t(stack_depth) * block * 4;
+  hipLaunchKernelGGL(closest_hit_kernel, dim3(unsigned(grid)), dim3(block), lds, s, nodes, tris,
+                     n_tris, stack_depth, n, orig, dir, skip, tmin, tmax, brute, out_tri, out_t);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
+                         const float* in_pol, float cyl_r, float zlo, float zhi, float* out_dir,
+                         float* out_pol, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(sample_kernel, dim3(unsigned(grid)), dim3(block), 0, s, kind, uint32_t(seed),
+                     uint32_t(seed >> 32), pid0, n, in_dir, in_pol, cyl_r, zlo, zhi, out_dir,
+                     out_pol);
+  return hipGetLastError();
+}
+
+}  // namespace xp

@@ -1,0 +1,120 @@
+// xp_internal.h -- data layouts shared by the host side and the gfx950 kernels
+// of the photon-transport library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/xephot.h"
+
+namespace xp {
+
+constexpr int kMaxMaterials = 8;
+constexpr int kMaxSurfaces = 16;
+constexpr int kCounterRing = 64;
+constexpr int kStatsWords = 16;
+
+// 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
+// reads the node with eight 16-byte loads.
+//   count[i] >  0 : leaf child, triangles [~child[i], ~child[i] + count[i])
+//   count[i] == 0 : inner child, node index child[i]
+//   count[i] <  0 : empty slot
+struct alignas(128) Node4 {
+  float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+  int32_t child[4];
+  int32_t count[4];
+};
+static_assert(sizeof(Node4) == 128, "Node4 must be one 128-byte line");
+
+// Triangle record in leaf order, three 16-byte vectors:
+//   a = (v0, bits(mesh triangle index)), b = (v1, bits(packed media/surface)),
+//   c = (v2, bits(sensor id)); packed = mat_in | mat_out << 8 | (surface + 1) << 16.
+struct alignas(16) TriRec {
+  float a[4], b[4], c[4];
+};
+static_assert(sizeof(TriRec) == 48, "TriRec is 48 bytes");
+
+struct DevMaterial {
+  float n, abs_len, ray_len, pad;
+};
+
+// Explicit surface as cumulative thresholds of one uniform draw.
+struct DevSurface {
+  float c_detect, c_absorb, c_diffuse, c_specular;  // cumulative sums, rounded once
+  float p_transmit, inv_r, inv_t;                    // 1/(R_diff+R_spec), 1/T
+  int32_t flags_grad;                                // flags | (grad_param + 1) << 8
+};
+
+enum Mode : int32_t { kForward = 0, kBackward = 1 };
+
+// Everything a propagate launch needs, passed by value (kernel arguments).
+struct LaunchArgs {
+  const Node4* nodes;
+  const TriRec* tris;
+  const int32_t* channel_of_sensor;
+  int32_t n_lds_nodes;
+  int32_t stack_depth;
+  int32_t n_channels;
+  int32_t n_sensors;
+  // sources
+  int32_t src_kind, medium;
+  int64_t n_photons, n_sources;
+  const float* positions;
+  const int64_t* offsets;
+  int64_t count_per_source;
+  int32_t per_source_events;
+  int32_t chunk;
+  const float* dirs;
+  const float* pols;
+  float cyl_r, cyl_zlo, cyl_zhi;
+  // run parameters
+  uint32_t seed_lo, seed_hi;
+  uint64_t pid_base;
+  int32_t max_steps;
+  float eps;
+  int32_t grad_material;
+  float surface_offset;
+  // outputs
+  int32_t* hit_map;
+  double* grad;
+  xp_photon_record* records;
+  unsigned long long* stats;
+  unsigned long long* work_counter;
+  const float* grad_hits;  // backward: upstream gradient per hit-map cell
+  double* grad_params;     // backward: 4 accumulated parameter gradients
+  DevMaterial mats[kMaxMaterials];
+  DevSurface surfs[kMaxSurfaces];
+};
+
+struct BvhResult {
+  std::vector<Node4> nodes;
+  std::vector<TriRec> tris;
+  int32_t depth = 0;
+  int32_t max_stack = 0;
+  std::vector<int32_t> level_end;  // level_end[l] = number of nodes in levels 0..l
+};
+
+// Host BVH build: binned SAH binary tree collapsed to 4-wide nodes in
+// breadth-first order; triangle records in leaf order.  Returns false and an
+// error message on failure.
+bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t* mat_in,
+                const int32_t* mat_out, const int32_t* surface, const int32_t* sensor,
+                int max_leaf, int bins, BvhResult& out, std::string& err);
+
+// Launch wrappers (defined in the kernel translation unit).
+hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
+hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
+                            int block, int grid, hipStream_t s);
+hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, int* out);
+hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_tris,
+                              int32_t stack_depth, int64_t n, const float* orig, const float* dir,
+                              const int32_t* skip, float tmin, float tmax, int32_t brute,
+                              int32_t* out_tri, float* out_t, hipStream_t s);
+hipError_t launch_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
+                         const float* in_pol, float cyl_r, float zlo, float zhi, float* out_dir,
+                         float* out_pol, hipStream_t s);
+
+}  // namespace xp

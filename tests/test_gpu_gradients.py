@@ -1,0 +1,143 @@
+"""Gradient tallies on the GPU: per-photon scores against the oracle, the
+backward replay against the contraction of the fused Jacobian, the analytic
+sphere, and common-random-number finite differences."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_14354_amd import workloads as W
+from tests.gpu_common import agreement, to_records
+from tests.helpers import face_average
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    assert torch.cuda.is_available()
+    from paper_2203_14354_amd import runtime
+    return runtime
+
+
+def _scores(rec, mats, gm=0):
+    L_a, L_r = mats[gm].abs_length, mats[gm].rayleigh_length
+    det = (rec["flag"] & 0xFF) == 1
+    s = np.zeros((len(rec), 4))
+    s[:, 0] = rec["path_len"] / L_a ** 2
+    s[:, 1] = rec["path_len"] / L_r ** 2 - rec["n_scatter"] / L_r
+    s[:, 2] = rec["sum_inv_r"]
+    s[:, 3] = rec["sum_inv_t"]
+    return s * det[:, None]
+
+
+def test_fused_tallies_match_records_and_oracle(rt):
+    wl = W.differentiable(n_points=3, photons_per_point=20_000)
+    det = rt.Detector(wl.mesh, device=0)
+    out = det.propagate(wl.sources, seed=7, grad=True, records=True)
+    torch.cuda.synchronize()
+    gpu = to_records(out["records"])
+    G = out["grad"].cpu().numpy()[0]
+    s = _scores(gpu, wl.mesh.materials)
+    # the tallies are the per-sensor sums of the per-photon scores (FP64 atomics)
+    detm = (gpu["flag"] & 0xFF) == 1
+    ref = np.zeros_like(G)
+    np.add.at(ref, gpu["sensor"][detm], s[detm])
+    assert np.allclose(G, ref, rtol=1e-5, atol=1e-6)
+    # per-photon scores of agreeing photons equal the oracle's (FP32 vs FP64)
+    orc = oracle.run(oracle.Scene(wl.mesh), wl.sources, seed=7, grad=True)
+    o = orc["records"]
+    ag = agreement(gpu, o)
+    assert ag.mean() >= 0.999
+    so = _scores(o, wl.mesh.materials)
+    m = ag & detm
+    assert np.allclose(s[m], so[m], rtol=1e-3, atol=1e-3)
+    assert np.array_equal(gpu["n_scatter"][m], o["n_scatter"][m])
+    # and the tallied Jacobian agrees with the oracle's within the disagreeing photons
+    diff = np.abs(G - orc["grad"][0]).sum(axis=0)
+    bound = np.abs(s[~ag]).sum(axis=0) + np.abs(so[~ag]).sum(axis=0) + 1e-3 * np.abs(G).sum(0)
+    assert np.all(diff <= bound + 1e-6)
+
+
+def test_backward_replay_equals_fused_contraction(rt):
+    wl = W.differentiable(n_points=4, photons_per_point=50_000)
+    det = rt.Detector(wl.mesh, device=0)
+    out = det.propagate(wl.sources, seed=3, grad=True)
+    g_out = torch.linspace(-1.0, 2.0, det.n_channels, device="cuda").reshape(1, -1)
+    gp = det.backward(wl.sources, g_out, seed=3)
+    torch.cuda.synchronize()
+    G = out["grad"].double()
+    expect = torch.einsum("ec,ecp->p", g_out.double(), G)
+    assert torch.allclose(gp, expect, rtol=1e-6, atol=1e-6)
+
+
+def test_autograd_function_both_modes(rt):
+    from paper_2203_14354_amd.autograd import base_params, hits
+    wl = W.differentiable(n_points=2, photons_per_point=50_000)
+    det = rt.Detector(wl.mesh, device=0)
+    p = base_params(wl.mesh).requires_grad_(True)
+    w = torch.arange(det.n_channels, dtype=torch.float64, device="cuda").reshape(1, -1)
+    grads = []
+    for mode in ("fused", "replay"):
+        h = hits(p, det, wl.sources, seed=5, mode=mode)
+        (h * w).sum().backward()
+        grads.append(p.grad.clone())
+        p.grad = None
+    assert torch.allclose(grads[0], grads[1], rtol=1e-6, atol=1e-6)
+    assert torch.all(torch.isfinite(grads[0]))
+
+
+def test_sphere_absorption_gradient_analytic(rt):
+    lam = 0.1
+    m = W.sphere(0.1, level=5, lam_abs=lam)
+    det = rt.Detector(m, device=0)
+    n = 2_000_000
+    out = det.propagate(W.point_sources([[0, 0, 0]], count_per_source=n), seed=2, grad=True,
+                        records=True)
+    torch.cuda.synchronize()
+    g = out["grad"].cpu().numpy()[0, 0] / n
+    P = out["hit_map"].sum().item() / n
+    expP = face_average(m.vertices, m.triangles, [0, 0, 0], lambda d: np.exp(-d / lam))
+    expG = face_average(m.vertices, m.triangles, [0, 0, 0], lambda d: d / lam ** 2 * np.exp(-d / lam))
+    assert abs(P - expP) < 4 * math.sqrt(expP * (1 - expP) / n)
+    rec = to_records(out["records"])
+    sc = np.where((rec["flag"] & 0xFF) == 1, rec["path_len"] / lam ** 2, 0.0)
+    assert abs(g[0] - expG) < 4 * sc.std() / math.sqrt(n)
+
+
+def _batched_estimates(det, src, params, seed, n_batches, per_batch, gm=0):
+    """Per-batch total hits and per-batch score tallies at the given parameters."""
+    from paper_2203_14354_amd.autograd import apply_params
+    apply_params(det, params, gm)
+    H, G = [], []
+    for b in range(n_batches):
+        out = det.propagate(src, seed=seed, pid_base=b * per_batch, n_photons=per_batch, grad=True)
+        H.append(out["hit_map"].sum())
+        G.append(out["grad"].sum(dim=(0, 1)))
+    torch.cuda.synchronize()
+    return torch.stack(H).double().cpu().numpy(), torch.stack(G).cpu().numpy()
+
+
+@pytest.mark.parametrize("p,h", [(0, 5.0), (1, 0.02), (2, 0.01), (3, 0.02)])
+def test_crn_finite_differences(rt, p, h):
+    """d(total hits)/d theta_p: score-function tallies against central finite
+    differences with common random numbers (same seed and photon ids), batch
+    means for the error bars."""
+    from paper_2203_14354_amd.autograd import base_params
+    nb, per = 40, 100_000
+    wl = W.differentiable(n_points=1, photons_per_point=nb * per)
+    det = rt.Detector(wl.mesh, device=0)
+    ds = det.sources(wl.sources)
+    p0 = base_params(wl.mesh).numpy()
+    _, G = _batched_estimates(det, ds, p0, 11, nb, per)
+    lo, hi = p0.copy(), p0.copy()
+    lo[p] -= h
+    hi[p] += h
+    Hl, _ = _batched_estimates(det, ds, lo, 11, nb, per)
+    Hh, _ = _batched_estimates(det, ds, hi, 11, nb, per)
+    fd = (Hh - Hl) / (2 * h)
+    sc = G[:, p]
+    se = math.sqrt(fd.var(ddof=1) / nb + sc.var(ddof=1) / nb)
+    assert abs(fd.mean() - sc.mean()) < 4 * se + 0.02 * abs(sc.mean()), (fd.mean(), sc.mean(), se)

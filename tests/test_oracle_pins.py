@@ -530,3 +530,15 @@ def test_zero_gradient_invariant_rayleigh(oracle_lib):
     s = rec["path_len"] / 0.05 ** 2 - rec["n_scatter"] / 0.05
     assert abs(out["grad"][0, 0, 1]) / n < 4 * s.std() / math.sqrt(n)
     assert rec["n_scatter"].mean() > 1.0  # the test exercises scattering
+
+
+def test_lambertian_basis_continuous_for_wall_normals(oracle_lib):
+    """A wall normal in the xy plane must give the same diffuse direction
+    whether rounding leaves its z component at +0, -0 or +-1e-12."""
+    outs = []
+    for nz in (0.0, -0.0, 1e-12, -1e-12):
+        n = np.array([0.6, 0.8, nz]) / np.linalg.norm([0.6, 0.8, nz])
+        d, _ = oracle_lib.sample(1, seed=3, pid0=0, n=1000, in_dir=n)
+        outs.append(d)
+    for d in outs[1:]:
+        assert np.abs(d - outs[0]).max() < 1e-9
