@@ -63,6 +63,7 @@ class XeHits(torch.autograd.Function):
         out = det.propagate(ds, seed=seed, grad=fused, grad_material=grad_material)
         ctx.det, ctx.ds, ctx.seed, ctx.mode, ctx.gm = det, ds, seed, mode, grad_material
         ctx.params = params.detach().cpu().clone()
+        ctx.params_device = params.device
         if fused:
             ctx.save_for_backward(out["grad"])
         return out["hit_map"].to(torch.float64)
@@ -75,7 +76,7 @@ class XeHits(torch.autograd.Function):
         else:
             apply_params(ctx.det, ctx.params, ctx.gm)
             gp = ctx.det.backward(ctx.ds, grad_out, seed=ctx.seed, grad_material=ctx.gm)
-        return gp.to(grad_out.device), None, None, None, None, None
+        return gp.to(ctx.params_device), None, None, None, None, None
 
 
 def hits(params: torch.Tensor, det, sources, seed=0, mode="fused", grad_material=0):

@@ -602,14 +602,17 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
     const int32_t fl = p.flag & 0xff;
     if (fl == F_DETECT) {
       const int64_t cell = int64_t(p.event) * a.n_channels + a.channel_of_sensor[p.sensor];
-      float sc[4] = {0.f, 0.f, 0.f, 0.f};
+      // score-function weights of the detected path, evaluated in FP64 (the
+      // Rayleigh-length score is a difference of two large terms)
+      double sc[4] = {0.0, 0.0, 0.0, 0.0};
       if (kGradAcc) {
         if (a.grad_material >= 0) {
           const DevMaterial gm = a.mats[a.grad_material];
-          const float s0 = p.path_len / (gm.abs_len * gm.abs_len);
-          const float s1 = p.path_len / (gm.ray_len * gm.ray_len) - float(p.n_sca) / gm.ray_len;
-          sc[0] = isfinite(s0) ? s0 : 0.0f;
-          sc[1] = isfinite(s1) ? s1 : 0.0f;
+          const double L = p.path_len, la = gm.abs_len, lr = gm.ray_len;
+          const double s0 = L / (la * la);
+          const double s1 = L / (lr * lr) - double(p.n_sca) / lr;
+          sc[0] = isfinite(s0) ? s0 : 0.0;
+          sc[1] = isfinite(s1) ? s1 : 0.0;
         }
         sc[2] = p.sum_inv_r;
         sc[3] = p.sum_inv_t;
@@ -618,12 +621,12 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
         if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
         if (kGrad && a.grad) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, double(sc[q]));
+          for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
         }
       } else {
         const double w = double(a.grad_hits[cell]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += w * double(sc[q]);
+        for (int q = 0; q < 4; ++q) acc[q] += w * sc[q];
       }
     }
     if (kRecords) {
