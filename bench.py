@@ -27,7 +27,7 @@ METRIC = "photons propagated/sec on DARWIN-scale TPC mesh; gradient-pass overhea
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 NODE_BYTES, TRI_BYTES = 128, 48
 KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
-                  "paper_2203_14354_amd/csrc/xp_internal.h"]
+                  "paper_2203_14354_amd/csrc/xp_internal.h", "paper_2203_14354_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
 
 
@@ -144,6 +144,7 @@ def main():
     if not args.no_extras:
         extras.update(gradient_overhead(torch, W, Detector, dev))
         extras.update(batched_vs_plain(torch, W, Detector, dev))
+        extras.update(lce_map_rate(torch, W, dev))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -222,6 +223,28 @@ def batched_vs_plain(torch, W, Detector, dev):
     return {"batched_s1": {"workload": f"4096 log-normal sources, {n} photons, per-event maps",
                            "photons_per_s": n / statistics.median(db),
                            "plain_forward_photons_per_s": n / statistics.median(dpl)}}
+
+
+def lce_map_rate(torch, W, dev):
+    """64^3 equal-volume cells x 1e4 photons (2.6e9 photons) on the small TPC
+    with the transparent plane: {top, bottom} counts and FP64 gradients per cell."""
+    from paper_2203_14354_amd import lcemap
+    det = lcemap.tpc1_lce_map_detector()
+    cen = W.equal_volume_cell_centroids(64, 64, 64, W.TPC1_SRC_R, -W.TPC1_SRC_ZHALF,
+                                        W.TPC1_SRC_ZHALF)
+    lcemap.lce_map(det, cen[:16384], 100, seed=4)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hits, g = lcemap.lce_map(det, cen, 10_000, seed=4, batch_cells=16384)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(cen) * 10_000
+    lce = hits.sum(dim=1).double() / 10_000
+    return {"lce_map": {"workload": "small TPC + plane, 64^3 cells x 1e4 photons, "
+                                    "{top, bottom} + 4 FP64 gradients per cell",
+                        "photons": n, "seconds": dt, "photons_per_s": n / dt,
+                        "mean_lce": float(lce.mean()), "min_lce": float(lce.min()),
+                        "max_lce": float(lce.max())}}
 
 
 def cpu_baseline(W, mesh, seed, sample):

@@ -1,8 +1,10 @@
 """Build the gfx950 transport library ``libxephot.so`` in-tree with hipcc.
 
 Device code is compiled for gfx950 only, with packed-FP32 instruction
-selection disabled (``-packed-fp32-ops``) and hardware floating-point atomics
-(``-munsafe-fp-atomics``) for the FP64 gradient tallies.
+selection disabled (``-packed-fp32-ops``), multiply-add fusion limited to
+single expressions (``-ffp-contract=on``, so that all kernel instantiations
+round alike) and hardware floating-point atomics (``-munsafe-fp-atomics``)
+for the FP64 gradient tallies.
 """
 from __future__ import annotations
 
@@ -42,7 +44,9 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
-    dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+    # -ffp-contract=on: multiply-adds fuse only within one expression, so every
+    # instantiation of the transport kernel rounds identically
+    dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     objs = []
     for s in HOST_SOURCES + DEVICE_SOURCES:

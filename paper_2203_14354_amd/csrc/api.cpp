@@ -15,7 +15,7 @@
 #include "xp_internal.h"
 
 namespace xp {
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_depth, int block);
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block);
 }
 
 struct xp_context {
@@ -43,6 +43,8 @@ struct xp_context {
   int32_t* d_channel = nullptr;
   int32_t d_channel_len = 0;
   unsigned long long* d_counters = nullptr;
+  int32_t* d_stack_overflow = nullptr;  // per-lane spill slots of the traversal stack
+  int64_t stack_overflow_lanes = 0;
   unsigned ring_next = 0;
   bool tuned = false;
   xp_launch_cfg tuned_cfg{};
@@ -107,7 +109,7 @@ int upload_channel_map(xp_context* ctx) {
   return XP_OK;
 }
 
-xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3}; }
+xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds}; }
 
 // Validates (ctx, src, rp) for a launch and fills the kernel arguments.
 int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
@@ -159,6 +161,9 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (lc.block_size == 0) lc.block_size = 256;
   if (lc.chunk <= 0) lc.chunk = 64;
   if (lc.lds_levels < 0) lc.lds_levels = 3;
+  if (lc.stack_lds == 0) lc.stack_lds = xp::kStackLds;
+  if (lc.stack_lds < 2 || lc.stack_lds > 64 || (lc.stack_lds & (lc.stack_lds - 1)))
+    return fail(ctx, XP_ERR_INVALID_ARG, "stack_lds must be a power of two in 2..64");
   if (lc.block_size != 64 && lc.block_size != 128 && lc.block_size != 256)
     return fail(ctx, XP_ERR_INVALID_ARG, "block_size must be 64, 128 or 256");
   if (lc.lds_levels > 4) return fail(ctx, XP_ERR_INVALID_ARG, "lds_levels must be <= 4");
@@ -170,7 +175,9 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.channel_of_sensor = ctx->d_channel;
   const int levels = std::min<int>(lc.lds_levels, int(ctx->bvh.level_end.size()));
   a.n_lds_nodes = levels > 0 ? ctx->bvh.level_end[levels - 1] : 0;
-  a.stack_depth = ctx->bvh.max_stack;
+  a.stack_lds = lc.stack_lds;
+  a.stack_total = ctx->bvh.max_stack;
+  a.stack_overflow = ctx->d_stack_overflow;
   a.n_channels = ctx->n_channels;
   a.n_sensors = ctx->max_sensor + 1;
   a.src_kind = src->kind;
@@ -216,7 +223,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.surfs[i].inv_t = s.p_transmit > 0 ? float(1.0 / double(s.p_transmit)) : 0.0f;
     a.surfs[i].flags_grad = (s.flags & 0xff) | ((s.grad_param + 1) << 8);
   }
-  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_depth, lc.block_size);
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size);
   if (lds > ctx->max_lds)
     return fail(ctx, XP_ERR_UNSUPPORTED, "LDS request of " + std::to_string(lds) +
                                              " bytes exceeds the device limit; use fewer lds_levels "
@@ -227,6 +234,8 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (per_cu <= 0) return fail(ctx, XP_ERR_UNSUPPORTED, "kernel does not fit on a CU");
   if (lc.blocks_per_cu <= 0 || lc.blocks_per_cu > per_cu) lc.blocks_per_cu = per_cu;
   grid = ctx->n_cu * lc.blocks_per_cu;
+  if (int64_t(grid) * lc.block_size > ctx->stack_overflow_lanes)
+    return fail(ctx, XP_ERR_UNSUPPORTED, "launch exceeds the traversal-stack overflow area");
   return XP_OK;
 }
 
@@ -291,6 +300,7 @@ void xp_context_destroy(xp_context* ctx) {
   dfree(ctx->d_tris);
   dfree(ctx->d_channel);
   dfree(ctx->d_counters);
+  dfree(ctx->d_stack_overflow);
   delete ctx;
 }
 
@@ -426,6 +436,8 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
+  if (int64_t(ctx->mat_in.size()) >= (int64_t(1) << 28))
+    return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
   if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
     return fail(ctx, XP_ERR_STATE, "channel map does not cover the mesh's sensor ids");
   try {
@@ -451,6 +463,13 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(nodes)");
     e = hipMemcpy(ctx->d_tris, r.tris.data(), r.tris.size() * sizeof(xp::TriRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(triangles)");
+    // spill slots for every lane that can be resident at once (allocated here,
+    // never inside a launch, so that launches can be captured in a graph)
+    dfree(ctx->d_stack_overflow);
+    ctx->stack_overflow_lanes = int64_t(ctx->n_cu) * xp::kMaxThreadsPerCu;
+    e = hipMalloc(&ctx->d_stack_overflow,
+                  size_t(ctx->stack_overflow_lanes) * size_t(r.max_stack) * sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(stack overflow)");
     const int rc = upload_channel_map(ctx);
     if (rc != XP_OK) return rc;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -550,44 +569,43 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     float best_ms = 1e30f;
     xp_launch_cfg best = default_cfg();
     int rc = XP_OK;
-    const int blocks[3] = {64, 128, 256};
-    const int levels[3] = {0, 2, 3};
-    const int chunks[2] = {64, 256};
-    for (int b : blocks)
-      for (int l : levels)
-        for (int c : chunks) {
-          xp_launch_cfg cand{b, 0, c, l};
-          xp::LaunchArgs a;
-          xp_launch_cfg cfg;
-          int grid = 0;
-          rc = prepare(ctx, &sample, rp, &cand, a, cfg, grid);
-          if (rc == XP_ERR_UNSUPPORTED) {
-            rc = XP_OK;
-            continue;
-          }
-          if (rc != XP_OK) break;
-          a.hit_map = d_map;
-          float ms_best = 1e30f;
-          for (int rep = 0; rep < 2; ++rep) {
-            (void)hipEventRecord(t0, s);
-            rc = launch(ctx, a, xp::kForward, false, false, false, cfg, grid, s);
-            if (rc != XP_OK) break;
-            (void)hipEventRecord(t1, s);
-            e = hipEventSynchronize(t1);
-            if (e != hipSuccess) {
-              rc = hip_fail(ctx, e, "autotune run");
-              break;
-            }
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, t0, t1);
-            ms_best = std::min(ms_best, ms);
-          }
-          if (rc != XP_OK) break;
-          if (ms_best < best_ms) {
-            best_ms = ms_best;
-            best = cfg;
-          }
+    std::vector<xp_launch_cfg> cands;
+    for (int b : {64, 128, 256})
+      for (int l : {0, 2, 3})
+        for (int c : {64, 256})
+          for (int sl : {8, 16}) cands.push_back(xp_launch_cfg{b, 0, c, l, sl});
+    for (const xp_launch_cfg& cand : cands) {
+      xp::LaunchArgs a;
+      xp_launch_cfg cfg;
+      int grid = 0;
+      rc = prepare(ctx, &sample, rp, &cand, a, cfg, grid);
+      if (rc == XP_ERR_UNSUPPORTED) {  // does not fit this device: skip the candidate
+        rc = XP_OK;
+        continue;
+      }
+      if (rc != XP_OK) break;
+      a.hit_map = d_map;
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 2 && rc == XP_OK; ++rep) {
+        (void)hipEventRecord(t0, s);
+        rc = launch(ctx, a, xp::kForward, false, false, false, cfg, grid, s);
+        if (rc != XP_OK) break;
+        (void)hipEventRecord(t1, s);
+        e = hipEventSynchronize(t1);
+        if (e != hipSuccess) {
+          rc = hip_fail(ctx, e, "autotune run");
+          break;
         }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ms_best = std::min(ms_best, ms);
+      }
+      if (rc != XP_OK) break;
+      if (ms_best < best_ms) {
+        best_ms = ms_best;
+        best = cfg;
+      }
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     (void)hipFree(d_map);
@@ -612,8 +630,10 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
   if (n >= (int64_t(1) << 37)) return fail(ctx, XP_ERR_INVALID_ARG, "too many rays");
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  int32_t depth_pow2 = 1;
+  while (depth_pow2 < ctx->bvh.max_stack) depth_pow2 <<= 1;
   const hipError_t e = xp::launch_closest_hit(
-      ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_triangles), ctx->bvh.max_stack, n, orig, dir,
+      ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_triangles), depth_pow2, n, orig, dir,
       skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(closest_hit)");
   return XP_OK;

@@ -235,18 +235,19 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
   for (size_t i = 0; i < level_of.size(); ++i) out.level_end[level_of[i]] = int32_t(i) + 1;
   for (int l = 1; l <= depth; ++l) out.level_end[l] = std::max(out.level_end[l], out.level_end[l - 1]);
 
-  // worst-case stack of the traversal: at each node all hit inner children but
-  // the one followed are pushed; need(node) = (inner children - 1) + max need(child)
+  // worst-case stack of the traversal: a visit pushes at most (children - 1)
+  // entries (inner nodes or leaves), one child being followed or postponed;
+  // need(node) = (children - 1) + max need(inner child)
   std::vector<int32_t> need(out.nodes.size(), 0);
   for (int64_t i = int64_t(out.nodes.size()) - 1; i >= 0; --i) {
     const Node4& nd = out.nodes[i];
-    int inner = 0, sub = 0;
-    for (int k = 0; k < 4; ++k)
-      if (nd.count[k] == 0) {
-        ++inner;
-        sub = std::max(sub, need[nd.child[k]]);
-      }
-    need[i] = std::max(0, inner - 1) + sub;
+    int kids = 0, sub = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (nd.count[k] < 0) continue;
+      ++kids;
+      if (nd.count[k] == 0) sub = std::max(sub, need[nd.child[k]]);
+    }
+    need[i] = std::max(0, kids - 1) + sub;
   }
   out.max_stack = need[0] + 1;
 

@@ -269,75 +269,157 @@ struct Counters {
   uint32_t nodes, tris;
 };
 
+// Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
+// from LDS, the rest from global memory.
+__device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, const float4* lds_nodes,
+                                           int32_t n_lds, int32_t node, float4 (&q)[8]) {
+  if (node < n_lds) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = lds_nodes[node * 8 + i];
+  } else {
+    const float4* g = reinterpret_cast<const float4*>(gnodes + node);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = g[i];
+  }
+}
+
+// Per-lane traversal stack: the newest `lds_cap` entries (a power of two) in
+// an LDS ring, older ones spilled to this lane's column of a global overflow
+// array.  `total` is the host-computed worst case; a push beyond it fails.
+struct LaneStack {
+  int32_t* lds;        // this lane's first LDS slot; slot k at lds[k * stride]
+  int32_t stride;
+  int32_t mask;        // lds_cap - 1
+  int32_t* glob;       // this lane's first overflow slot; slot k at glob[k * gstride]
+  int64_t gstride;
+  int32_t total;
+  int32_t sp, base;    // entries in use; entries held in the overflow array
+  __device__ __forceinline__ bool push(int32_t e) {
+    if (sp >= total) return false;
+    if (sp - base > mask) {  // ring full: move the oldest entry to the overflow array
+      glob[int64_t(base) * gstride] = lds[(base & mask) * stride];
+      ++base;
+    }
+    lds[(sp & mask) * stride] = e;
+    ++sp;
+    return true;
+  }
+  __device__ __forceinline__ int32_t pop() {
+    --sp;
+    if (sp < base) {
+      base = sp;
+      return glob[int64_t(sp) * gstride];
+    }
+    return lds[(sp & mask) * stride];
+  }
+};
+
+// compare-exchange of (key, value) pairs: ascending keys
+__device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t& vb) {
+  const bool sw = kb < ka;
+  const float k = sw ? kb : ka;
+  const int32_t v = sw ? vb : va;
+  kb = sw ? ka : kb;
+  vb = sw ? va : vb;
+  ka = k;
+  va = v;
+}
+
 // BVH closest hit: t in (tmin, b.t], ties to the lower triangle index.
+//
+// One loop in which every iteration a lane does one of three things: test
+// the triangles of its postponed leaf, visit one inner node, or pop its
+// stack.  Lanes of a wave therefore stay in the same loop whatever mix of
+// leaves and nodes they meet, instead of running divergent triangle loops
+// nested in the child loop.  A visited node's hit children are ordered by
+// entry distance; the nearest inner child is followed, the nearest leaf is
+// postponed (one slot), and the rest are pushed far-first.  Stack entries are
+// node indices (>= 0) or complemented packed leaves (first << 3 | count - 1).
+// Returns false only if the stack would overflow its host-computed bound.
 template <bool kCount>
 __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
                                          int32_t n_lds, const TriRec* __restrict__ tris,
-                                         int32_t* stack, int32_t stride, int32_t depth_cap, f3 o,
-                                         f3 d, float tmin, int32_t skip, Best& b, Counters& cnt) {
+                                         LaneStack st, f3 o, f3 d, float tmin, int32_t skip,
+                                         Best& b, Counters& cnt) {
   const RayW ray = make_ray(o, d);
   const float tiny = 1e-30f;
   const f3 inv{1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
                1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
                1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z))};
   const f3 oi{o.x * inv.x, o.y * inv.y, o.z * inv.z};
-  int32_t node = 0;
-  int32_t sp = 0;
+  int32_t node = 0;   // inner node to visit next, or -1
+  int32_t leaf = -1;  // postponed leaf (packed), or -1
+  st.sp = 0;
+  st.base = 0;
   while (true) {
-    float4 q[8];
-    if (node < n_lds) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) q[i] = lds_nodes[node * 8 + i];
-    } else {
-      const float4* g = reinterpret_cast<const float4*>(gnodes + node);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) q[i] = g[i];
-    }
-    if (kCount) cnt.nodes++;
-    const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
-    const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
-    const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
-    const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
-    const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
-    const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
-    const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
-                              __float_as_int(q[6].z), __float_as_int(q[6].w)};
-    const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
-                              __float_as_int(q[7].z), __float_as_int(q[7].w)};
-    int32_t next = -1;
-    float next_t = kInfF;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (count[i] < 0) continue;
-      const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
-      const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
-      const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
-      const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-      const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b.t));
-      if (!(tn <= tf * 1.0000005f)) continue;
-      if (count[i] > 0) {
-        const int32_t first = ~child[i];
-        for (int32_t k = first; k < first + count[i]; ++k) {
-          if (kCount) cnt.tris++;
-          test_triangle(tris, k, ray, tmin, skip, b);
-        }
-      } else if (tn < next_t) {
-        if (next >= 0) {
-          if (sp >= depth_cap) return false;
-          stack[sp++ * stride] = next;
-        }
-        next = child[i];
-        next_t = tn;
-      } else {
-        if (sp >= depth_cap) return false;
-        stack[sp++ * stride] = child[i];
+    if (leaf >= 0) {
+      const int32_t first = leaf >> 3, n = (leaf & 7) + 1;
+      for (int32_t k = first; k < first + n; ++k) {
+        if (kCount) cnt.tris++;
+        test_triangle(tris, k, ray, tmin, skip, b);
       }
-    }
-    if (next >= 0) {
-      node = next;
+      leaf = -1;
+    } else if (node >= 0) {
+      float4 q[8];
+      fetch_node(gnodes, lds_nodes, n_lds, node, q);
+      if (kCount) cnt.nodes++;
+      const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+      const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
+      const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
+      const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
+      const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
+      const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
+      const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
+                                __float_as_int(q[6].z), __float_as_int(q[6].w)};
+      const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
+                                __float_as_int(q[7].z), __float_as_int(q[7].w)};
+      float key[4];
+      int32_t ent[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
+        const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
+        const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
+        const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+        const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b.t));
+        const bool hit = count[i] >= 0 && tn <= tf * 1.0000005f;
+        key[i] = hit ? tn : kInfF;
+        ent[i] = count[i] > 0 ? ~((~child[i] << 3) | (count[i] - 1)) : child[i];
+      }
+      // ascending entry distance (a 5-comparator network); misses sort last
+      cswap(key[0], ent[0], key[1], ent[1]);
+      cswap(key[2], ent[2], key[3], ent[3]);
+      cswap(key[0], ent[0], key[2], ent[2]);
+      cswap(key[1], ent[1], key[3], ent[3]);
+      cswap(key[1], ent[1], key[2], ent[2]);
+      node = -1;
+#pragma unroll
+      for (int i = 3; i >= 0; --i) {
+        if (key[i] == kInfF) continue;
+        const int32_t e = ent[i];
+        const bool is_leaf = e < 0;
+        // the nearest inner child is followed and the nearest leaf postponed;
+        // what they displace is pushed (farther entries first)
+        int32_t spill = e;
+        if (is_leaf && leaf < 0) {
+          leaf = ~e;
+          spill = -1 - 0x7fffffff;
+        } else if (is_leaf) {
+          spill = ~leaf;
+          leaf = ~e;
+        } else if (node < 0) {
+          node = e;
+          spill = -1 - 0x7fffffff;
+        } else {
+          spill = node;
+          node = e;
+        }
+        if (spill != -1 - 0x7fffffff && !st.push(spill)) return false;
+      }
     } else {
-      if (sp == 0) break;
-      node = stack[--sp * stride];
+      if (st.sp == 0) break;
+      const int32_t e = st.pop();
+      if (e >= 0) node = e; else leaf = ~e;
     }
   }
   return true;
@@ -396,8 +478,8 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
 // ---------------------------------------------------------------------------
 template <bool kGradAcc, bool kCount>
 __device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint64_t pid,
-                                            const float4* lds_nodes, int32_t* stack,
-                                            int32_t stride, Counters& cnt) {
+                                            const float4* lds_nodes, const LaneStack& stack,
+                                            Counters& cnt) {
   const int32_t step = ++p.steps;
   const DevMaterial m = a.mats[p.medium];
   const R4 r = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 0u);
@@ -405,8 +487,8 @@ __device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint
   const float d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
   const float d_bulk = fminf(d_abs, d_sca);
   Best b{d_bulk, -1, -1};
-  if (!traverse<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, a.tris, stack, stride, a.stack_depth,
-                        p.pos, p.dir, a.eps, p.last_tri, b, cnt)) {
+  if (!traverse<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, a.tris, stack, p.pos, p.dir, a.eps,
+                        p.last_tri, b, cnt)) {
     p.flag |= F_NAN_ABORT;  // traversal stack exhausted (prevented by the host's sizing)
     return true;
   }
@@ -544,14 +626,15 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
   float4* lds_nodes = lds;
   int32_t* stack_base = reinterpret_cast<int32_t*>(lds + a.n_lds_nodes * 8);
   unsigned long long* blk_stats =
-      reinterpret_cast<unsigned long long*>(stack_base + a.stack_depth * blockDim.x);
+      reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
   const float4* gn = reinterpret_cast<const float4*>(a.nodes);
   for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
   if (kCount)
     for (int32_t i = threadIdx.x; i < kStatsWords; i += blockDim.x) blk_stats[i] = 0ull;
   __syncthreads();
-  int32_t* stack = stack_base + threadIdx.x;
-  const int32_t stride = blockDim.x;
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  LaneStack stack{stack_base + threadIdx.x, int32_t(blockDim.x), a.stack_lds - 1,
+                  a.stack_overflow + gtid, int64_t(gridDim.x) * blockDim.x, a.stack_total, 0, 0};
   const uint32_t lane = lane_rank(~0ull);
 
   Photon p;
@@ -595,7 +678,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
     if (!alive) continue;
 
     // ---- one step of the live photon ----
-    const bool ended = step_photon<kGradAcc, kCount>(p, a, pid, lds_nodes, stack, stride, cnt);
+    const bool ended = step_photon<kGradAcc, kCount>(p, a, pid, lds_nodes, stack, cnt);
     if (kCount) n_steps++;
     if (!ended) continue;
     alive = false;
@@ -676,7 +759,9 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
                                                          float tmin, float tmax, int32_t brute,
                                                          int32_t* out_tri, float* out_t) {
   extern __shared__ float4 lds[];
-  int32_t* stack = reinterpret_cast<int32_t*>(lds) + threadIdx.x;
+  // the whole worst-case stack in LDS (stack_depth is a power of two here)
+  LaneStack stack{reinterpret_cast<int32_t*>(lds) + threadIdx.x, int32_t(blockDim.x),
+                  stack_depth - 1, nullptr, 0, stack_depth, 0, 0};
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const f3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
@@ -691,8 +776,7 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   } else {
     // no node is staged (n_lds = 0); the LDS base is passed rather than a null
     // pointer, which this toolchain's inliner fails on
-    ok = traverse<false>(nodes, lds, 0, tris, stack, blockDim.x, stack_depth, o, d, tmin, sk, b,
-                         c);
+    ok = traverse<false>(nodes, lds, 0, tris, stack, o, d, tmin, sk, b, c);
   }
   out_tri[i] = ok ? b.tri : -2;
   out_t[i] = b.tri >= 0 ? b.t : kInfF;
@@ -737,8 +821,8 @@ hipError_t launch_one(const LaunchArgs& a, int block, int grid, size_t lds, hipS
 
 }  // namespace
 
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_depth, int block) {
-  return size_t(n_lds_nodes) * sizeof(Node4) + size_t(stack_depth) * block * 4 +
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block) {
+  return size_t(n_lds_nodes) * sizeof(Node4) + size_t(stack_lds) * block * 4 +
          kStatsWords * sizeof(unsigned long long);
 }
 
@@ -749,7 +833,7 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
 
 hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
                             int block, int grid, hipStream_t s) {
-  const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_depth, block);
+  const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block);
   if (mode == kBackward) {
     if (records || count || grad) return hipErrorInvalidValue;
     return launch_one<kBackward, false, false, false>(a, block, grid, lds, s);

@@ -16,6 +16,8 @@ constexpr int kMaxMaterials = 8;
 constexpr int kMaxSurfaces = 16;
 constexpr int kCounterRing = 64;
 constexpr int kStatsWords = 16;
+constexpr int kStackLds = 16;        // LDS ring entries per lane
+constexpr int kMaxThreadsPerCu = 2048;
 
 // 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
 // reads the node with eight 16-byte loads.
@@ -56,7 +58,9 @@ struct LaunchArgs {
   const TriRec* tris;
   const int32_t* channel_of_sensor;
   int32_t n_lds_nodes;
-  int32_t stack_depth;
+  int32_t stack_lds;       // LDS ring entries per lane (power of two)
+  int32_t stack_total;     // worst-case stack entries of the BVH
+  int32_t* stack_overflow; // [stack_total][grid * block] spill slots
   int32_t n_channels;
   int32_t n_sensors;
   // sources

@@ -68,3 +68,22 @@ def test_autotuned_config_gives_identical_results(det):
     b = det.propagate(wl.sources, seed=1, launch=cfg)["hit_map"]
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_lce_map_batch_invariance_and_oracle():
+    from paper_2203_14354_amd import lcemap
+    det = lcemap.tpc1_lce_map_detector()
+    cen = W.equal_volume_cell_centroids(6, 6, 6, W.TPC1_SRC_R, -W.TPC1_SRC_ZHALF,
+                                        W.TPC1_SRC_ZHALF)
+    h1, g1 = lcemap.lce_map(det, cen, 500, seed=3, batch_cells=216)
+    h2, g2 = lcemap.lce_map(det, cen, 500, seed=3, batch_cells=50)
+    torch.cuda.synchronize()
+    assert torch.equal(h1, h2)
+    assert torch.allclose(g1, g2, rtol=1e-9, atol=1e-9)
+    mesh = W.tpc1(plane=True)
+    sc = oracle.Scene(mesh, channel_of_sensor=W.tpc1_top_bottom_channels(mesh), n_channels=2)
+    h = h1.cpu().numpy()
+    for c in (0, 77, 215):
+        src = W.point_sources(cen[c:c + 1], count_per_source=500, per_source_events=True)
+        ref = oracle.run(sc, src, seed=3, pid_base=c * 500)["hit_map"][0]
+        assert np.abs(ref - h[c]).max() <= 1, (c, ref, h[c])

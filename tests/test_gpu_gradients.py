@@ -28,10 +28,11 @@ def _scores(rec, mats, gm=0):
     L_r = float(np.float32(mats[gm].rayleigh_length))
     det = (rec["flag"] & 0xFF) == 1
     s = np.zeros((len(rec), 4))
-    s[:, 0] = rec["path_len"] / L_a ** 2
-    s[:, 1] = rec["path_len"] / L_r ** 2 - rec["n_scatter"] / L_r
-    s[:, 2] = rec["sum_inv_r"]
-    s[:, 3] = rec["sum_inv_t"]
+    L = rec["path_len"].astype(np.float64)
+    s[:, 0] = L / L_a ** 2
+    s[:, 1] = L / L_r ** 2 - rec["n_scatter"].astype(np.float64) / L_r
+    s[:, 2] = rec["sum_inv_r"].astype(np.float64)
+    s[:, 3] = rec["sum_inv_t"].astype(np.float64)
     return s * det[:, None]
 
 

@@ -134,9 +134,12 @@ def test_small_tpc_per_photon_parity(rt, tpc1_det, tpc1_scene):
     assert np.quantile(err, 0.999) < 1e-5 and err.max() < 1e-3
 
 
-@pytest.mark.parametrize("cfg", [dict(block_size=64, blocks_per_cu=1, chunk=1, lds_levels=0),
-                                 dict(block_size=128, blocks_per_cu=0, chunk=256, lds_levels=2),
-                                 dict(block_size=256, blocks_per_cu=2, chunk=64, lds_levels=4)])
+@pytest.mark.parametrize("cfg", [dict(block_size=64, blocks_per_cu=1, chunk=1, lds_levels=0,
+                                      stack_lds=2),
+                                 dict(block_size=128, blocks_per_cu=0, chunk=256, lds_levels=2,
+                                      stack_lds=4),
+                                 dict(block_size=256, blocks_per_cu=2, chunk=64, lds_levels=4,
+                                      stack_lds=64)])
 def test_launch_configuration_does_not_change_results(rt, tpc1_det, cfg):
     wl = W.small_tpc(photons_per_point=20_000)
     a = tpc1_det.propagate(wl.sources, seed=3)["hit_map"]
@@ -212,6 +215,19 @@ def test_tir_at_75_degrees_on_quartz(rt):
     gpu = to_records(out["records"])
     assert np.all(gpu["medium"] == 0)          # nobody entered the quartz
     assert np.all(gpu["dir"][:, 2] < 0)        # all reflected downwards
+
+
+def test_stack_spill_to_global_does_not_change_results(rt):
+    """A 2-entry LDS ring forces deep traversals to spill to the global overflow
+    area; the DARWIN hit map must not change."""
+    mesh = W.darwin()
+    det = rt.Detector(mesh, device=0)
+    src = W.darwin_tpc(n_photons=400_000, mesh=mesh).sources
+    a = det.propagate(src, seed=2)["hit_map"]
+    b = det.propagate(src, seed=2, launch=dict(block_size=256, blocks_per_cu=0, chunk=64,
+                                               lds_levels=3, stack_lds=2))["hit_map"]
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
 
 
 def test_darwin_parity_sampled(rt):
