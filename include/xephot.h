@@ -214,6 +214,10 @@ typedef struct xp_launch_cfg {
   int32_t stack_lds;       /* traversal-stack entries per lane kept in LDS, a power of
                               two in 2..64 (0 = default 16); deeper entries spill to a
                               global overflow area allocated by xp_build_bvh */
+  int32_t wave_batch;      /* photons per wave interaction phase: a wave interrupts its
+                              closest-hit searches to run the interactions, tallies and
+                              refills once at least this many of its 64 lanes are not
+                              searching, 1..64 (0 = default 32) */
 } xp_launch_cfg;
 
 /* One per photon (indexed by the launch-local photon index), written when
@@ -239,7 +243,9 @@ typedef struct xp_photon_record {
  *   d_stats    device uint64 [16] or NULL: ACCUMULATES counters
  *              [0..7] photons per terminal flag (index = flag low byte),
  *              [8] GEOMETRY_ERROR photons, [9] steps, [10] BVH nodes visited,
- *              [11] triangles tested (counting mode costs time).
+ *              [11] triangles tested, [12] node-phase lane slots offered and
+ *              [13] used by live photons (SIMD utilization of traversal)
+ *              (counting mode costs time).
  *   lc         NULL = the context's tuned or default configuration.
  * Errors: XP_ERR_STATE (no BVH / tables), XP_ERR_INVALID_ARG, XP_ERR_HIP.
  * Concurrency: calls on one context use a ring of 64 work counters; at most

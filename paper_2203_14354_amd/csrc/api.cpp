@@ -109,7 +109,7 @@ int upload_channel_map(xp_context* ctx) {
   return XP_OK;
 }
 
-xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds}; }
+xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds, xp::kWaveBatch}; }
 
 // Validates (ctx, src, rp) for a launch and fills the kernel arguments.
 int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
@@ -162,6 +162,9 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (lc.chunk <= 0) lc.chunk = 64;
   if (lc.lds_levels < 0) lc.lds_levels = 3;
   if (lc.stack_lds == 0) lc.stack_lds = xp::kStackLds;
+  if (lc.wave_batch == 0) lc.wave_batch = xp::kWaveBatch;
+  if (lc.wave_batch < 1 || lc.wave_batch > 64)
+    return fail(ctx, XP_ERR_INVALID_ARG, "wave_batch must be in 1..64");
   if (lc.stack_lds < 2 || lc.stack_lds > 64 || (lc.stack_lds & (lc.stack_lds - 1)))
     return fail(ctx, XP_ERR_INVALID_ARG, "stack_lds must be a power of two in 2..64");
   if (lc.block_size != 64 && lc.block_size != 128 && lc.block_size != 256)
@@ -189,6 +192,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.count_per_source = src->count_per_source;
   a.per_source_events = src->kind == XP_SRC_POINTS ? src->per_source_events : 0;
   a.chunk = lc.chunk;
+  a.wave_batch = lc.wave_batch;
   a.dirs = src->directions;
   a.pols = src->polarizations;
   a.cyl_r = src->cyl_radius;
@@ -570,10 +574,10 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     xp_launch_cfg best = default_cfg();
     int rc = XP_OK;
     std::vector<xp_launch_cfg> cands;
-    for (int b : {64, 128, 256})
-      for (int l : {0, 2, 3})
-        for (int c : {64, 256})
-          for (int sl : {8, 16}) cands.push_back(xp_launch_cfg{b, 0, c, l, sl});
+    for (int b : {64, 256})
+      for (int l : {0, 3})
+        for (int sl : {8, 16})
+          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb});
     for (const xp_launch_cfg& cand : cands) {
       xp::LaunchArgs a;
       xp_launch_cfg cfg;

@@ -267,6 +267,7 @@ __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, i
 
 struct Counters {
   uint32_t nodes, tris;
+  uint32_t slots, busy;  // node-phase lane slots offered / used (SIMD utilization)
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
@@ -325,16 +326,75 @@ __device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t
   va = v;
 }
 
+// Visit one inner node: test its four child boxes, order the hits by entry
+// distance, follow the nearest inner child, postpone the nearest leaf (the
+// slot is free when a node is visited) and push the rest far-first.  Stack
+// entries are node indices (>= 0) or complemented packed leaves
+// (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
+template <bool kCount>
+__device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
+                                           const float4* lds_nodes, int32_t n_lds, f3 inv, f3 oi,
+                                           float tmax, LaneStack& st, int32_t& node,
+                                           int32_t& leaf, Counters& cnt) {
+  float4 q[8];
+  fetch_node(gnodes, lds_nodes, n_lds, node, q);
+  if (kCount) cnt.nodes++;
+  const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
+  const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
+  const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
+  const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
+  const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
+  const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
+  const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
+                            __float_as_int(q[6].z), __float_as_int(q[6].w)};
+  const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
+                            __float_as_int(q[7].z), __float_as_int(q[7].w)};
+  float key[4];
+  int32_t ent[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
+    const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
+    const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    const bool hit = count[i] >= 0 && tn <= tf * 1.0000005f;
+    key[i] = hit ? tn : kInfF;
+    ent[i] = count[i] > 0 ? ~((~child[i] << 3) | (count[i] - 1)) : child[i];
+  }
+  // ascending entry distance (a 5-comparator network); misses sort last
+  cswap(key[0], ent[0], key[1], ent[1]);
+  cswap(key[2], ent[2], key[3], ent[3]);
+  cswap(key[0], ent[0], key[2], ent[2]);
+  cswap(key[1], ent[1], key[3], ent[3]);
+  cswap(key[1], ent[1], key[2], ent[2]);
+  node = -1;
+  constexpr int32_t kNone = -1 - 0x7fffffff;
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    if (key[i] == kInfF) continue;
+    const int32_t e = ent[i];
+    int32_t spill = kNone;
+    if (e < 0) {  // leaf: the nearer one keeps the slot
+      if (leaf >= 0) spill = ~leaf;
+      leaf = ~e;
+    } else {      // inner node: the nearer one is followed
+      if (node >= 0) spill = node;
+      node = e;
+    }
+    if (spill != kNone && !st.push(spill)) return false;
+  }
+  return true;
+}
+
 // BVH closest hit: t in (tmin, b.t], ties to the lower triangle index.
 //
-// One loop in which every iteration a lane does one of three things: test
-// the triangles of its postponed leaf, visit one inner node, or pop its
-// stack.  Lanes of a wave therefore stay in the same loop whatever mix of
-// leaves and nodes they meet, instead of running divergent triangle loops
-// nested in the child loop.  A visited node's hit children are ordered by
-// entry distance; the nearest inner child is followed, the nearest leaf is
-// postponed (one slot), and the rest are pushed far-first.  Stack entries are
-// node indices (>= 0) or complemented packed leaves (first << 3 | count - 1).
+// Two phases that the lanes of a wave run in step.  Node phase: each lane
+// without a postponed leaf visits inner nodes (popping its stack when it has
+// none) until every lane of the wave holds a leaf or has run out of work.
+// Leaf phase: every lane holding a leaf tests its triangles.  Running the
+// phases separately keeps the wave's lanes on the same code (node tests or
+// triangle tests) instead of paying for both in every iteration.
 // Returns false only if the stack would overflow its host-computed bound.
 template <bool kCount>
 __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
@@ -349,9 +409,34 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
   const f3 oi{o.x * inv.x, o.y * inv.y, o.z * inv.z};
   int32_t node = 0;   // inner node to visit next, or -1
   int32_t leaf = -1;  // postponed leaf (packed), or -1
+  bool ok = true;
   st.sp = 0;
   st.base = 0;
   while (true) {
+    // ---- node phase ----
+    while (true) {
+      const bool active = leaf < 0 && (node >= 0 || st.sp > 0);
+      if (kCount) {
+        cnt.slots++;
+        if (active) cnt.busy++;
+      }
+      if (active) {
+        if (node < 0) {
+          const int32_t e = st.pop();
+          if (e >= 0) node = e; else leaf = ~e;
+        }
+        if (node >= 0 && leaf < 0) {
+          if (!visit_node<kCount>(gnodes, lds_nodes, n_lds, inv, oi, b.t, st, node, leaf, cnt)) {
+            ok = false;
+            node = -1;
+            leaf = -1;
+            st.sp = 0;
+          }
+        }
+      }
+      if (__ballot(leaf < 0 && (node >= 0 || st.sp > 0)) == 0ull) break;
+    }
+    // ---- leaf phase ----
     if (leaf >= 0) {
       const int32_t first = leaf >> 3, n = (leaf & 7) + 1;
       for (int32_t k = first; k < first + n; ++k) {
@@ -359,70 +444,10 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
         test_triangle(tris, k, ray, tmin, skip, b);
       }
       leaf = -1;
-    } else if (node >= 0) {
-      float4 q[8];
-      fetch_node(gnodes, lds_nodes, n_lds, node, q);
-      if (kCount) cnt.nodes++;
-      const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
-      const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
-      const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
-      const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
-      const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
-      const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
-      const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
-                                __float_as_int(q[6].z), __float_as_int(q[6].w)};
-      const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
-                                __float_as_int(q[7].z), __float_as_int(q[7].w)};
-      float key[4];
-      int32_t ent[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
-        const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
-        const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
-        const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-        const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b.t));
-        const bool hit = count[i] >= 0 && tn <= tf * 1.0000005f;
-        key[i] = hit ? tn : kInfF;
-        ent[i] = count[i] > 0 ? ~((~child[i] << 3) | (count[i] - 1)) : child[i];
-      }
-      // ascending entry distance (a 5-comparator network); misses sort last
-      cswap(key[0], ent[0], key[1], ent[1]);
-      cswap(key[2], ent[2], key[3], ent[3]);
-      cswap(key[0], ent[0], key[2], ent[2]);
-      cswap(key[1], ent[1], key[3], ent[3]);
-      cswap(key[1], ent[1], key[2], ent[2]);
-      node = -1;
-#pragma unroll
-      for (int i = 3; i >= 0; --i) {
-        if (key[i] == kInfF) continue;
-        const int32_t e = ent[i];
-        const bool is_leaf = e < 0;
-        // the nearest inner child is followed and the nearest leaf postponed;
-        // what they displace is pushed (farther entries first)
-        int32_t spill = e;
-        if (is_leaf && leaf < 0) {
-          leaf = ~e;
-          spill = -1 - 0x7fffffff;
-        } else if (is_leaf) {
-          spill = ~leaf;
-          leaf = ~e;
-        } else if (node < 0) {
-          node = e;
-          spill = -1 - 0x7fffffff;
-        } else {
-          spill = node;
-          node = e;
-        }
-        if (spill != -1 - 0x7fffffff && !st.push(spill)) return false;
-      }
-    } else {
-      if (st.sp == 0) break;
-      const int32_t e = st.pop();
-      if (e >= 0) node = e; else leaf = ~e;
     }
+    if (__ballot(node >= 0 || st.sp > 0) == 0ull) break;
   }
-  return true;
+  return ok;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,24 +499,40 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
 }
 
 // ---------------------------------------------------------------------------
-// one transport step; returns true when the photon has ended
+// one transport step, in two halves around the closest-hit search
 // ---------------------------------------------------------------------------
-template <bool kGradAcc, bool kCount>
-__device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint64_t pid,
-                                            const float4* lds_nodes, const LaneStack& stack,
-                                            Counters& cnt) {
+struct StepDraw {
+  float d_abs, d_sca, u2;  // free paths to absorption and scattering; decision uniform
+};
+
+// Start step s = steps + 1: draw the free paths in the current medium.
+__device__ __forceinline__ StepDraw begin_step(Photon& p, const LaunchArgs& a, uint64_t pid) {
   const int32_t step = ++p.steps;
   const DevMaterial m = a.mats[p.medium];
   const R4 r = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 0u);
-  const float d_abs = isinf(m.abs_len) ? kInfF : -m.abs_len * logf(r.u0);
-  const float d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
-  const float d_bulk = fminf(d_abs, d_sca);
-  Best b{d_bulk, -1, -1};
-  if (!traverse<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, a.tris, stack, p.pos, p.dir, a.eps,
-                        p.last_tri, b, cnt)) {
-    p.flag |= F_NAN_ABORT;  // traversal stack exhausted (prevented by the host's sizing)
+  StepDraw sd;
+  sd.d_abs = isinf(m.abs_len) ? kInfF : -m.abs_len * logf(r.u0);
+  sd.d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
+  sd.u2 = r.u2;
+  return sd;
+}
+
+// Finish the step given the closest hit b within min(d_abs, d_sca) (b.tri < 0:
+// none; b.tri == kTraversalFailed: the stack bound was exceeded).  Returns
+// true when the photon has ended.
+constexpr int32_t kTraversalFailed = -2;
+
+template <bool kGradAcc>
+__device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint64_t pid,
+                                            const StepDraw& sd, const Best& b) {
+  if (b.tri == kTraversalFailed) {
+    p.flag |= F_NAN_ABORT;  // prevented by the host's stack sizing
     return true;
   }
+  const int32_t step = p.steps;
+  const DevMaterial m = a.mats[p.medium];
+  const float d_abs = sd.d_abs, d_sca = sd.d_sca;
+  const float d_bulk = fminf(d_abs, d_sca);
   const bool in_grad = p.medium == a.grad_material;
   if (b.tri < 0) {
     if (isinf(d_bulk)) {
@@ -540,7 +581,7 @@ __device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint
         p.flag |= F_SURFACE_ABSORB;
         return true;
       }
-      const float u = r.u2;
+      const float u = sd.u2;
       if (u < s.c_detect) {
         if (is_sensor) {
           p.flag |= F_DETECT;
@@ -579,7 +620,7 @@ __device__ __forceinline__ bool step_photon(Photon& p, const LaunchArgs& a, uint
     } else {
       const float n1 = a.mats[m_from].n, n2 = a.mats[m_to].n;
       bool through = true;
-      if (n1 != n2) through = fresnel(p, n_back, n1, n2, r.u2);
+      if (n1 != n2) through = fresnel(p, n_back, n1, n2, sd.u2);
       if (through) p.medium = m_to;
       p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
     }
@@ -618,7 +659,20 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // ---------------------------------------------------------------------------
 // the persistent transport kernel
 //   kMode: kForward (hit map, optional gradient tallies) or kBackward (replay)
+//
+// Every lane is EMPTY (no photon), TRAVERSING (searching the closest hit of
+// its photon's current step) or WAITING (hit found, interaction pending).
+// Each loop iteration every traversing lane takes one micro-step of its BVH
+// search: a stack pop, then one leaf's triangle tests or one node visit.  When
+// at least `wave_batch` lanes of the wave are not traversing, the wave runs one
+// combined phase for all of them: the interaction of the waiting lanes (and
+// the tallies of photons that end), the refill of empty lanes from the photon
+// pool, and the start of the next step (free paths, ray set-up).  Lanes thus
+// never wait for the slowest search of the wave, and the long, branchy
+// interaction code runs once for many lanes instead of once per step.
 // ---------------------------------------------------------------------------
+enum : int32_t { kEmpty = 0, kTraversing = 1, kWaiting = 2 };
+
 template <int kMode, bool kGrad, bool kRecords, bool kCount>
 __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
   extern __shared__ float4 lds[];
@@ -636,94 +690,151 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
   LaneStack stack{stack_base + threadIdx.x, int32_t(blockDim.x), a.stack_lds - 1,
                   a.stack_overflow + gtid, int64_t(gridDim.x) * blockDim.x, a.stack_total, 0, 0};
   const uint32_t lane = lane_rank(~0ull);
+  const uint32_t batch_trigger = 64u - uint32_t(a.wave_batch);  // run the phase at <= this
 
   Photon p;
-  bool alive = false;
+  int32_t state = kEmpty;
   int64_t idx = 0;
   uint64_t pid = 0;
   uint64_t pool_next = 0, pool_end = 0;
   bool exhausted = false;
-  Counters cnt{0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u};
   uint32_t n_steps = 0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // search state of the current step
+  StepDraw sd{0.f, 0.f, 0.f};
+  Best b{0.f, -1, -1};
+  RayW ray;
+  f3 inv{0.f, 0.f, 0.f}, oi{0.f, 0.f, 0.f};
+  int32_t node = -1, leaf = -1;
 
   while (true) {
-    // ---- refill lanes whose photon has ended (wave-uniform control flow) ----
-    uint64_t dead = __ballot(!alive);
-    while (dead != 0ull && !exhausted) {
-      if (pool_next >= pool_end) {
-        uint64_t base = 0;
-        if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
-        base = bcast64(base);
-        if (base >= uint64_t(a.n_photons)) {
-          exhausted = true;
-          break;
-        }
-        pool_next = base;
-        pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
-      }
-      const uint64_t avail = pool_end - pool_next;
-      const uint32_t rank = lane_rank(dead);
-      if (!alive && rank < avail) {
-        idx = int64_t(pool_next + rank);
-        pid = a.pid_base + uint64_t(idx);
-        emit(p, a, idx, pid);
-        alive = true;
-      }
-      const uint64_t ndead = uint64_t(__popcll(dead));
-      pool_next += ndead < avail ? ndead : avail;
-      dead = __ballot(!alive);
-    }
-    if (__ballot(alive) == 0ull) break;
-    if (!alive) continue;
-
-    // ---- one step of the live photon ----
-    const bool ended = step_photon<kGradAcc, kCount>(p, a, pid, lds_nodes, stack, cnt);
-    if (kCount) n_steps++;
-    if (!ended) continue;
-    alive = false;
-    const int32_t fl = p.flag & 0xff;
-    if (fl == F_DETECT) {
-      const int64_t cell = int64_t(p.event) * a.n_channels + a.channel_of_sensor[p.sensor];
-      // score-function weights of the detected path, evaluated in FP64 (the
-      // Rayleigh-length score is a difference of two large terms)
-      double sc[4] = {0.0, 0.0, 0.0, 0.0};
-      if (kGradAcc) {
-        if (a.grad_material >= 0) {
-          const DevMaterial gm = a.mats[a.grad_material];
-          const double L = p.path_len, la = gm.abs_len, lr = gm.ray_len;
-          const double s0 = L / (la * la);
-          const double s1 = L / (lr * lr) - double(p.n_sca) / lr;
-          sc[0] = isfinite(s0) ? s0 : 0.0;
-          sc[1] = isfinite(s1) ? s1 : 0.0;
-        }
-        sc[2] = p.sum_inv_r;
-        sc[3] = p.sum_inv_t;
-      }
-      if (kMode == kForward) {
-        if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
-        if (kGrad && a.grad) {
+    const uint32_t n_trav = uint32_t(__popcll(__ballot(state == kTraversing)));
+    if (n_trav <= batch_trigger) {
+      // ---- interaction of the waiting lanes ----
+      bool start = false;  // lanes that begin a new step in this phase
+      if (state == kWaiting) {
+        state = kTraversing;  // a new step follows unless the photon ends
+        start = true;
+        if (finish_step<kGradAcc>(p, a, pid, sd, b)) {
+          start = false;
+          state = kEmpty;
+          const int32_t fl = p.flag & 0xff;
+          if (fl == F_DETECT) {
+            const int64_t cell = int64_t(p.event) * a.n_channels + a.channel_of_sensor[p.sensor];
+            // score-function weights of the detected path, evaluated in FP64 (the
+            // Rayleigh-length score is a difference of two large terms)
+            double sc[4] = {0.0, 0.0, 0.0, 0.0};
+            if (kGradAcc) {
+              if (a.grad_material >= 0) {
+                const DevMaterial gm = a.mats[a.grad_material];
+                const double L = p.path_len, la = gm.abs_len, lr = gm.ray_len;
+                const double s0 = L / (la * la);
+                const double s1 = L / (lr * lr) - double(p.n_sca) / lr;
+                sc[0] = isfinite(s0) ? s0 : 0.0;
+                sc[1] = isfinite(s1) ? s1 : 0.0;
+              }
+              sc[2] = p.sum_inv_r;
+              sc[3] = p.sum_inv_t;
+            }
+            if (kMode == kForward) {
+              if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
+              if (kGrad && a.grad) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
+                for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
+              }
+            } else {
+              const double w = double(a.grad_hits[cell]);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q] += w * sc[q];
+            }
+          }
+          if (kRecords) {
+            xp_photon_record& rec = a.records[idx];
+            rec.flag = p.flag; rec.last_tri = p.last_tri; rec.sensor = p.sensor; rec.steps = p.steps;
+            rec.event = p.event; rec.medium = p.medium; rec.n_scatter = p.n_sca; rec.reserved = 0;
+            rec.pos[0] = p.pos.x; rec.pos[1] = p.pos.y; rec.pos[2] = p.pos.z; rec.time = p.time;
+            rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z;
+            rec.path_len = p.path_len;
+            rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z;
+            rec.sum_inv_r = p.sum_inv_r;
+            rec.sum_inv_t = p.sum_inv_t; rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
+          }
+          if (kCount) {
+            atomicAdd(&blk_stats[fl], 1ull);
+            if (p.flag & F_GEOM) atomicAdd(&blk_stats[8], 1ull);
+          }
+        }
+      }
+      // ---- refill empty lanes from the photon pool (wave-uniform control flow) ----
+      uint64_t dead = __ballot(state == kEmpty);
+      while (dead != 0ull && !exhausted) {
+        if (pool_next >= pool_end) {
+          uint64_t base = 0;
+          if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
+          base = bcast64(base);
+          if (base >= uint64_t(a.n_photons)) {
+            exhausted = true;
+            break;
+          }
+          pool_next = base;
+          pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
+        }
+        const uint64_t avail = pool_end - pool_next;
+        const uint32_t rank = lane_rank(dead);
+        if (state == kEmpty && rank < avail) {
+          idx = int64_t(pool_next + rank);
+          pid = a.pid_base + uint64_t(idx);
+          state = kTraversing;
+          start = true;
+          emit(p, a, idx, pid);
+        }
+        const uint64_t ndead = uint64_t(__popcll(dead));
+        pool_next += ndead < avail ? ndead : avail;
+        dead = __ballot(state == kEmpty);
+      }
+      if (__ballot(state != kEmpty) == 0ull) break;  // pool exhausted and every lane idle
+      // ---- start the next step of the lanes that continue or just got a photon ----
+      if (start) {
+        sd = begin_step(p, a, pid);
+        b = Best{fminf(sd.d_abs, sd.d_sca), -1, -1};
+        ray = make_ray(p.pos, p.dir);
+        const float tiny = 1e-30f;
+        inv = f3{1.0f / (fabsf(p.dir.x) > tiny ? p.dir.x : copysignf(tiny, p.dir.x)),
+                 1.0f / (fabsf(p.dir.y) > tiny ? p.dir.y : copysignf(tiny, p.dir.y)),
+                 1.0f / (fabsf(p.dir.z) > tiny ? p.dir.z : copysignf(tiny, p.dir.z))};
+        oi = f3{p.pos.x * inv.x, p.pos.y * inv.y, p.pos.z * inv.z};
+        node = 0;
+        leaf = -1;
+        stack.sp = 0;
+        stack.base = 0;
+        if (kCount) n_steps++;
+      }
+    }
+    // ---- one micro-step of every traversing lane's closest-hit search ----
+    if (kCount) cnt.slots++;
+    if (state == kTraversing) {
+      if (kCount) cnt.busy++;
+      if (leaf < 0 && node < 0 && stack.sp > 0) {
+        const int32_t e = stack.pop();
+        if (e >= 0) node = e; else leaf = ~e;
+      }
+      if (leaf >= 0) {
+        const int32_t first = leaf >> 3, n = (leaf & 7) + 1;
+        for (int32_t k = first; k < first + n; ++k) {
+          if (kCount) cnt.tris++;
+          test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
+        }
+        leaf = -1;
+      } else if (node >= 0) {
+        if (!visit_node<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf,
+                                cnt)) {
+          b.tri = kTraversalFailed;
+          state = kWaiting;
         }
       } else {
-        const double w = double(a.grad_hits[cell]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += w * sc[q];
+        state = kWaiting;  // search complete: b holds the closest hit (or none)
       }
-    }
-    if (kRecords) {
-      xp_photon_record& rec = a.records[idx];
-      rec.flag = p.flag; rec.last_tri = p.last_tri; rec.sensor = p.sensor; rec.steps = p.steps;
-      rec.event = p.event; rec.medium = p.medium; rec.n_scatter = p.n_sca; rec.reserved = 0;
-      rec.pos[0] = p.pos.x; rec.pos[1] = p.pos.y; rec.pos[2] = p.pos.z; rec.time = p.time;
-      rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z; rec.path_len = p.path_len;
-      rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z; rec.sum_inv_r = p.sum_inv_r;
-      rec.sum_inv_t = p.sum_inv_t; rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
-    }
-    if (kCount) {
-      atomicAdd(&blk_stats[fl], 1ull);
-      if (p.flag & F_GEOM) atomicAdd(&blk_stats[8], 1ull);
     }
   }
 
@@ -739,13 +850,17 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
     const unsigned long long s9 = wave_sum_u64(n_steps);
     const unsigned long long s10 = wave_sum_u64(cnt.nodes);
     const unsigned long long s11 = wave_sum_u64(cnt.tris);
+    const unsigned long long s12 = wave_sum_u64(cnt.slots);
+    const unsigned long long s13 = wave_sum_u64(cnt.busy);
     if (lane == 0) {
       atomicAdd(&blk_stats[9], s9);
       atomicAdd(&blk_stats[10], s10);
       atomicAdd(&blk_stats[11], s11);
+      atomicAdd(&blk_stats[12], s12);
+      atomicAdd(&blk_stats[13], s13);
     }
     __syncthreads();
-    if (threadIdx.x < 12 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
+    if (threadIdx.x < 14 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
   }
 }
 
@@ -768,7 +883,7 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   const f3 d{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
   const int32_t sk = skip ? skip[i] : -1;
   Best b{tmax, -1, -1};
-  Counters c{0u, 0u};
+  Counters c{0u, 0u, 0u, 0u};
   bool ok = true;
   if (brute) {
     const RayW r = make_ray(o, d);

@@ -17,6 +17,7 @@ constexpr int kMaxSurfaces = 16;
 constexpr int kCounterRing = 64;
 constexpr int kStatsWords = 16;
 constexpr int kStackLds = 16;        // LDS ring entries per lane
+constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
 
 // 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
@@ -71,6 +72,7 @@ struct LaunchArgs {
   int64_t count_per_source;
   int32_t per_source_events;
   int32_t chunk;
+  int32_t wave_batch;      // lanes not searching before a wave runs its interaction phase
   const float* dirs;
   const float* pols;
   float cyl_r, cyl_zlo, cyl_zhi;

@@ -46,7 +46,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Surface) == 28
     assert ctypes.sizeof(_lib.Sources) == 88
     assert ctypes.sizeof(_lib.RunParams) == 32
-    assert ctypes.sizeof(_lib.LaunchCfg) == 20
+    assert ctypes.sizeof(_lib.LaunchCfg) == 24
     assert _lib.RECORD_DTYPE.itemsize == 96
 
 

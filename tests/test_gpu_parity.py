@@ -135,11 +135,11 @@ def test_small_tpc_per_photon_parity(rt, tpc1_det, tpc1_scene):
 
 
 @pytest.mark.parametrize("cfg", [dict(block_size=64, blocks_per_cu=1, chunk=1, lds_levels=0,
-                                      stack_lds=2),
+                                      stack_lds=2, wave_batch=1),
                                  dict(block_size=128, blocks_per_cu=0, chunk=256, lds_levels=2,
-                                      stack_lds=4),
+                                      stack_lds=4, wave_batch=64),
                                  dict(block_size=256, blocks_per_cu=2, chunk=64, lds_levels=4,
-                                      stack_lds=64)])
+                                      stack_lds=64, wave_batch=17)])
 def test_launch_configuration_does_not_change_results(rt, tpc1_det, cfg):
     wl = W.small_tpc(photons_per_point=20_000)
     a = tpc1_det.propagate(wl.sources, seed=3)["hit_map"]
@@ -225,7 +225,8 @@ def test_stack_spill_to_global_does_not_change_results(rt):
     src = W.darwin_tpc(n_photons=400_000, mesh=mesh).sources
     a = det.propagate(src, seed=2)["hit_map"]
     b = det.propagate(src, seed=2, launch=dict(block_size=256, blocks_per_cu=0, chunk=64,
-                                               lds_levels=3, stack_lds=2))["hit_map"]
+                                               lds_levels=3, stack_lds=2,
+                                               wave_batch=32))["hit_map"]
     torch.cuda.synchronize()
     assert torch.equal(a, b)
 
