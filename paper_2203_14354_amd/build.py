@@ -3,8 +3,10 @@
 Device code is compiled for gfx950 only, with packed-FP32 instruction
 selection disabled (``-packed-fp32-ops``), multiply-add fusion limited to
 single expressions (``-ffp-contract=on``, so that all kernel instantiations
-round alike) and hardware floating-point atomics (``-munsafe-fp-atomics``)
-for the FP64 gradient tallies.
+round alike), FP32 division and square root from the hardware approximations
+(``-fno-hip-fp32-correctly-rounded-divide-sqrt``; a few ulp, far inside the
+parity tolerances) and hardware floating-point atomics
+(``-munsafe-fp-atomics``) for the FP64 gradient tallies.
 """
 from __future__ import annotations
 
@@ -46,7 +48,11 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
     # -ffp-contract=on: multiply-adds fuse only within one expression, so every
     # instantiation of the transport kernel rounds identically
+    # -fno-hip-fp32-correctly-rounded-divide-sqrt: FP32 division and square root
+    # by the hardware reciprocal/root instructions (a few ulp) instead of the
+    # multi-instruction correctly rounded sequences
     dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics", "-ffp-contract=on",
+           "-fno-hip-fp32-correctly-rounded-divide-sqrt",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     objs = []
     for s in HOST_SOURCES + DEVICE_SOURCES:

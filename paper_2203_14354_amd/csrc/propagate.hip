@@ -820,12 +820,11 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
         if (e >= 0) node = e; else leaf = ~e;
       }
       if (leaf >= 0) {
-        const int32_t first = leaf >> 3, n = (leaf & 7) + 1;
-        for (int32_t k = first; k < first + n; ++k) {
-          if (kCount) cnt.tris++;
-          test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
-        }
-        leaf = -1;
+        // one triangle per micro-step: the packed leaf advances to its next triangle
+        const int32_t k = leaf >> 3, rest = leaf & 7;
+        if (kCount) cnt.tris++;
+        test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
+        leaf = rest > 0 ? (((k + 1) << 3) | (rest - 1)) : -1;
       } else if (node >= 0) {
         if (!visit_node<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf,
                                 cnt)) {
