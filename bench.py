@@ -134,10 +134,13 @@ def main():
     alg_bytes = NODE_BYTES * n_nodes + TRI_BYTES * n_tris
     kern_s = statistics.mean(durations)
     achieved = alg_bytes / kern_s
-    traffic = measured_traffic(N)
+    traffic_bytes = measured_traffic(N)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": traffic,
+                "frac": achieved / HBM_PEAK,
+                "traffic": None if traffic_bytes is None else traffic_bytes / kern_s / 1e9,
+                "traffic_bytes_per_launch": traffic_bytes,
                 "algorithmic_bytes_per_launch": alg_bytes,
+                "search_lane_utilization": (st[13] / st[12]) if st[12] else None,
                 "kernel": "propagate_kernel<forward>", "avg_launch_s": kern_s}
 
     extras = {}

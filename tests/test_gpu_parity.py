@@ -247,14 +247,15 @@ def test_darwin_parity_sampled(rt):
     torch.cuda.synchronize()
     assert torch.equal(plain, out["hit_map"])
     sc = oracle.Scene(mesh, use_bvh=True)
-    idx = np.sort(np.random.default_rng(0).choice(len(gpu), 3000, replace=False))
+    idx = np.sort(np.random.default_rng(0).choice(len(gpu), 20_000, replace=False))
     ag = []
     for i in idx:
         r = oracle.run(sc, src, seed=0, i_begin=int(i), i_end=int(i) + 1)["records"][0]
         g = gpu[i]
         ag.append(r["flag"] == g["flag"] and r["last_tri"] == g["last_tri"] and
                   r["steps"] == g["steps"] and r["sensor"] == g["sensor"])
-    assert np.mean(ag) >= 0.995, np.mean(ag)
+    # divergences come from FP32 positions within ~1e-7 m of the 0.5 mm strip edges
+    assert np.mean(ag) >= 0.999, np.mean(ag)
     # medium inconsistencies need an FP32 position on the wrong side of a surface
     # by more than the restart offset: at most 1e-5 of the photons
     assert st[8] <= 10, st[8]
