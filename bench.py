@@ -27,7 +27,8 @@ METRIC = "photons propagated/sec on DARWIN-scale TPC mesh; gradient-pass overhea
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 NODE_BYTES, TRI_BYTES = 128, 48
 KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
-                  "paper_2203_14354_amd/csrc/xp_internal.h", "paper_2203_14354_amd/build.py"]
+                  "paper_2203_14354_amd/csrc/safety.cpp", "paper_2203_14354_amd/csrc/xp_internal.h",
+                  "paper_2203_14354_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
 
 
@@ -167,6 +168,9 @@ def main():
                        "triangles_per_step": n_tris / n_steps,
                        "detected_fraction": st[1] / N, "bulk_absorbed_fraction": st[4] / N,
                        "surface_absorbed_fraction": st[3] / N,
+                       "search_skipped_fraction": st[14] / n_steps,
+                       "phase_cycle_fraction": st[16] / max(st[16] + st[17], 1),
+                       "lane_steps_per_phase": n_steps / max(st[15], 1),
                        "geometry_errors": st[8], "escaped": st[5], "max_steps": st[6],
                        "nan_aborts": st[7]},
         "kernel_sources_sha256_16": kernel_hash(),

@@ -139,6 +139,10 @@ int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_
 typedef struct xp_bvh_options {
   int32_t max_leaf_size;   /* triangles per leaf, 1..8 (default 4) */
   int32_t sah_bins;        /* SAH bins per axis, 4..64 (default 32) */
+  int32_t safety_cells;    /* cells of the safety grid along the mesh's longest extent,
+                              0..512 (0 = no grid, also when opts is NULL).  A step whose free
+                              path is shorter than the grid's distance bound skips the
+                              closest-hit search; results are identical either way */
 } xp_bvh_options;
 
 typedef struct xp_bvh_stats {
@@ -148,6 +152,8 @@ typedef struct xp_bvh_stats {
   int32_t max_stack;       /* worst-case traversal stack entries */
   int64_t node_bytes, triangle_bytes;
   double build_seconds;
+  int32_t safety_dims[3];  /* safety grid cells per axis (0 = no grid) */
+  float safety_cell;       /* cell size (m) */
 } xp_bvh_info;
 
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
@@ -240,12 +246,14 @@ typedef struct xp_photon_record {
  *              (L_abs, L_Rayleigh of grad_material, reflectivity, transparency),
  *              i.e. the Jacobian of the expected hits.
  *   d_records  device xp_photon_record [n_photons] or NULL.
- *   d_stats    device uint64 [16] or NULL: ACCUMULATES counters
+ *   d_stats    device uint64 [24] or NULL: ACCUMULATES counters
  *              [0..7] photons per terminal flag (index = flag low byte),
  *              [8] GEOMETRY_ERROR photons, [9] steps, [10] BVH nodes visited,
- *              [11] triangles tested, [12] node-phase lane slots offered and
- *              [13] used by live photons (SIMD utilization of traversal)
- *              (counting mode costs time).
+ *              [11] triangles tested, [12] search lane-slots offered and
+ *              [13] used (SIMD utilization of the search), [14] steps whose
+ *              search the safety grid skipped, [15] wave interaction phases,
+ *              [16] / [17] wave clock cycles spent in interaction phases / in
+ *              search micro-steps (counting mode costs time).
  *   lc         NULL = the context's tuned or default configuration.
  * Errors: XP_ERR_STATE (no BVH / tables), XP_ERR_INVALID_ARG, XP_ERR_HIP.
  * Concurrency: calls on one context use a ring of 64 work counters; at most
@@ -292,6 +300,15 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
 int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
               const float* in_pol, float cyl_radius, float cyl_zlo, float cyl_zhi, float* out_dir,
               float* out_pol, xp_stream stream);
+
+/* Host-only (no device needed): build the safety grid of a mesh (host arrays)
+ * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,
+ * out_lo float[3] the grid origin, *out_cell the cell size; out_values
+ * (float[dims product], may be NULL to query the size) the per-cell distance
+ * lower bounds, x fastest.  Errors: XP_ERR_INVALID_ARG, XP_ERR_MESH. */
+int xp_safety_grid_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                        int32_t cells_longest, int32_t* out_dims, float* out_lo, float* out_cell,
+                        float* out_values);
 
 /* Library version string. */
 const char* xp_version(void);

@@ -41,14 +41,16 @@ class Surface(ctypes.Structure):
 
 
 class BvhOptions(ctypes.Structure):
-    _fields_ = [("max_leaf_size", ctypes.c_int32), ("sah_bins", ctypes.c_int32)]
+    _fields_ = [("max_leaf_size", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
+                ("safety_cells", ctypes.c_int32)]
 
 
 class BvhInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
                 ("depth", ctypes.c_int32), ("max_stack", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int64), ("triangle_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double)]
+                ("build_seconds", ctypes.c_double), ("safety_dims", ctypes.c_int32 * 3),
+                ("safety_cell", ctypes.c_float)]
 
 
 class Sources(ctypes.Structure):
@@ -88,7 +90,7 @@ assert RECORD_DTYPE.itemsize == 96
 EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_mesh",
            "xp_set_materials", "xp_set_surfaces", "xp_set_channel_map", "xp_build_bvh",
            "xp_bvh_stats", "xp_propagate", "xp_backward", "xp_autotune", "xp_closest_hit",
-           "xp_sample", "xp_version"]
+           "xp_sample", "xp_safety_grid_host", "xp_version"]
 
 _lib = None
 
@@ -119,6 +121,7 @@ def load():
         "xp_autotune": (ctypes.c_int, [P, P, P, I64, P, P]),
         "xp_closest_hit": (ctypes.c_int, [P, I64, P, P, P, F, F, I32, P, P, P]),
         "xp_sample": (ctypes.c_int, [I32, U64, U64, I64, P, P, F, F, F, P, P, P]),
+        "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
         "xp_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -43,6 +43,8 @@ struct xp_context {
   int32_t* d_channel = nullptr;
   int32_t d_channel_len = 0;
   unsigned long long* d_counters = nullptr;
+  float* d_safety = nullptr;            // safety grid values
+  xp::SafetyGrid safety;                // grid geometry (values released after upload)
   int32_t* d_stack_overflow = nullptr;  // per-lane spill slots of the traversal stack
   int64_t stack_overflow_lanes = 0;
   unsigned ring_next = 0;
@@ -181,6 +183,12 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.stack_lds = lc.stack_lds;
   a.stack_total = ctx->bvh.max_stack;
   a.stack_overflow = ctx->d_stack_overflow;
+  a.safety = ctx->d_safety;
+  for (int k = 0; k < 3; ++k) {
+    a.sg_n[k] = ctx->safety.n[k];
+    a.sg_lo[k] = ctx->safety.lo[k];
+  }
+  a.sg_inv_cell = ctx->safety.inv_cell;
   a.n_channels = ctx->n_channels;
   a.n_sensors = ctx->max_sensor + 1;
   a.src_kind = src->kind;
@@ -305,6 +313,7 @@ void xp_context_destroy(xp_context* ctx) {
   dfree(ctx->d_channel);
   dfree(ctx->d_counters);
   dfree(ctx->d_stack_overflow);
+  dfree(ctx->d_safety);
   delete ctx;
 }
 
@@ -438,8 +447,11 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
   const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
   const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
+  const int scells = opts ? opts->safety_cells : 0;
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
+  if (scells < 0 || scells > 512)
+    return fail(ctx, XP_ERR_INVALID_ARG, "safety_cells must be in 0..512");
   if (int64_t(ctx->mat_in.size()) >= (int64_t(1) << 28))
     return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
   if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
@@ -453,6 +465,9 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
                         ctx->mat_out.data(), ctx->surf.data(), ctx->sensor.data(), leaf, bins, r, err))
       return fail(ctx, XP_ERR_MESH, err);
     if (r.max_stack > 512) return fail(ctx, XP_ERR_UNSUPPORTED, "BVH too deep");
+    xp::SafetyGrid sg;
+    if (!xp::build_safety_grid(ctx->vtx.data(), ctx->tri.data(), nt, scells, sg, err))
+      return fail(ctx, XP_ERR_UNSUPPORTED, err);
     DeviceGuard g(ctx->device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     ctx->bvh_built = false;
@@ -469,6 +484,18 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(triangles)");
     // spill slots for every lane that can be resident at once (allocated here,
     // never inside a launch, so that launches can be captured in a graph)
+    dfree(ctx->d_safety);
+    ctx->safety = xp::SafetyGrid();
+    if (!sg.values.empty()) {
+      e = hipMalloc(&ctx->d_safety, sg.values.size() * sizeof(float));
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(safety grid)");
+      e = hipMemcpy(ctx->d_safety, sg.values.data(), sg.values.size() * sizeof(float),
+                    hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(safety grid)");
+      sg.values.clear();
+      sg.values.shrink_to_fit();
+      ctx->safety = sg;
+    }
     dfree(ctx->d_stack_overflow);
     ctx->stack_overflow_lanes = int64_t(ctx->n_cu) * xp::kMaxThreadsPerCu;
     e = hipMalloc(&ctx->d_stack_overflow,
@@ -484,6 +511,8 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     ctx->stats.node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
     ctx->stats.triangle_bytes = int64_t(r.tris.size() * sizeof(xp::TriRec));
     ctx->stats.build_seconds = secs;
+    for (int k = 0; k < 3; ++k) ctx->stats.safety_dims[k] = ctx->safety.n[k];
+    ctx->stats.safety_cell = ctx->safety.inv_cell > 0 ? 1.0f / ctx->safety.inv_cell : 0.0f;
     r.nodes.clear();
     r.nodes.shrink_to_fit();
     r.tris.clear();
@@ -641,6 +670,31 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
       skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(closest_hit)");
   return XP_OK;
+}
+
+int xp_safety_grid_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                        int32_t cells_longest, int32_t* out_dims, float* out_lo, float* out_cell,
+                        float* out_values) {
+  if (!vtx || !tri || nv <= 0 || nt <= 0 || !out_dims || !out_lo || !out_cell ||
+      cells_longest < 1 || cells_longest > 512)
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad safety-grid arguments");
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] < 0 || tri[i] >= nv) return fail(nullptr, XP_ERR_MESH, "vertex index out of range");
+  try {
+    xp::SafetyGrid g;
+    std::string err;
+    if (!xp::build_safety_grid(vtx, tri, nt, cells_longest, g, err))
+      return fail(nullptr, XP_ERR_MESH, err);
+    for (int k = 0; k < 3; ++k) {
+      out_dims[k] = g.n[k];
+      out_lo[k] = g.lo[k];
+    }
+    *out_cell = 1.0f / g.inv_cell;
+    if (out_values) std::copy(g.values.begin(), g.values.end(), out_values);
+    return XP_OK;
+  } catch (...) {
+    return fail(nullptr, XP_ERR_OOM, "host allocation failed");
+  }
 }
 
 int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,

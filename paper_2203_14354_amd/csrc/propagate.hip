@@ -267,7 +267,8 @@ __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, i
 
 struct Counters {
   uint32_t nodes, tris;
-  uint32_t slots, busy;  // node-phase lane slots offered / used (SIMD utilization)
+  uint32_t slots, busy;  // search lane slots offered / used (SIMD utilization)
+  uint32_t skipped;      // searches skipped by the safety grid
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
@@ -517,6 +518,19 @@ __device__ __forceinline__ StepDraw begin_step(Photon& p, const LaunchArgs& a, u
   return sd;
 }
 
+// Lower bound of the distance from p to every triangle (0 outside the grid or
+// without one).
+__device__ __forceinline__ float safety_at(const LaunchArgs& a, f3 p) {
+  if (a.safety == nullptr) return 0.0f;
+  const float fx = (p.x - a.sg_lo[0]) * a.sg_inv_cell;
+  const float fy = (p.y - a.sg_lo[1]) * a.sg_inv_cell;
+  const float fz = (p.z - a.sg_lo[2]) * a.sg_inv_cell;
+  if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f)) return 0.0f;
+  const int32_t x = int32_t(fx), y = int32_t(fy), z = int32_t(fz);
+  if (x >= a.sg_n[0] || y >= a.sg_n[1] || z >= a.sg_n[2]) return 0.0f;
+  return a.safety[(int64_t(z) * a.sg_n[1] + y) * a.sg_n[0] + x];
+}
+
 // Finish the step given the closest hit b within min(d_abs, d_sca) (b.tri < 0:
 // none; b.tri == kTraversalFailed: the stack bound was exceeded).  Returns
 // true when the photon has ended.
@@ -698,7 +712,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
   uint64_t pid = 0;
   uint64_t pool_next = 0, pool_end = 0;
   bool exhausted = false;
-  Counters cnt{0u, 0u, 0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u, 0u};
   uint32_t n_steps = 0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   // search state of the current step
@@ -708,9 +722,13 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
   f3 inv{0.f, 0.f, 0.f}, oi{0.f, 0.f, 0.f};
   int32_t node = -1, leaf = -1;
 
+  unsigned long long cyc_phase = 0, cyc_search = 0, n_phases = 0;
   while (true) {
     const uint32_t n_trav = uint32_t(__popcll(__ballot(state == kTraversing)));
+    unsigned long long t_mark = 0;
+    if (kCount) t_mark = clock64();
     if (n_trav <= batch_trigger) {
+      if (kCount) n_phases++;
       // ---- interaction of the waiting lanes ----
       bool start = false;  // lanes that begin a new step in this phase
       if (state == kWaiting) {
@@ -809,10 +827,21 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
         stack.sp = 0;
         stack.base = 0;
         if (kCount) n_steps++;
+        // no triangle is closer than the cell's safety distance: a shorter free
+        // path cannot reach one, and the search's answer is "no hit"
+        if (b.t < safety_at(a, p.pos)) {
+          state = kWaiting;
+          if (kCount) cnt.skipped++;
+        }
       }
     }
     // ---- one micro-step of every traversing lane's closest-hit search ----
-    if (kCount) cnt.slots++;
+    if (kCount) {
+      const unsigned long long t_now = clock64();
+      cyc_phase += t_now - t_mark;
+      t_mark = t_now;
+      cnt.slots++;
+    }
     if (state == kTraversing) {
       if (kCount) cnt.busy++;
       if (leaf < 0 && node < 0 && stack.sp > 0) {
@@ -835,6 +864,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
         state = kWaiting;  // search complete: b holds the closest hit (or none)
       }
     }
+    if (kCount) cyc_search += clock64() - t_mark;
   }
 
   // ---- per-wave reductions at exit ----
@@ -851,15 +881,20 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
     const unsigned long long s11 = wave_sum_u64(cnt.tris);
     const unsigned long long s12 = wave_sum_u64(cnt.slots);
     const unsigned long long s13 = wave_sum_u64(cnt.busy);
+    const unsigned long long s14 = wave_sum_u64(cnt.skipped);
     if (lane == 0) {
       atomicAdd(&blk_stats[9], s9);
       atomicAdd(&blk_stats[10], s10);
       atomicAdd(&blk_stats[11], s11);
       atomicAdd(&blk_stats[12], s12);
       atomicAdd(&blk_stats[13], s13);
+      atomicAdd(&blk_stats[14], s14);
+      atomicAdd(&blk_stats[15], n_phases);
+      atomicAdd(&blk_stats[16], cyc_phase);
+      atomicAdd(&blk_stats[17], cyc_search);
     }
     __syncthreads();
-    if (threadIdx.x < 14 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
+    if (threadIdx.x < 18 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
   }
 }
 
@@ -882,7 +917,7 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   const f3 d{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
   const int32_t sk = skip ? skip[i] : -1;
   Best b{tmax, -1, -1};
-  Counters c{0u, 0u, 0u, 0u};
+  Counters c{0u, 0u, 0u, 0u, 0u};
   bool ok = true;
   if (brute) {
     const RayW r = make_ray(o, d);

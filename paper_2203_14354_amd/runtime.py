@@ -67,7 +67,7 @@ class Detector:
     """A mesh + optical tables + BVH resident on one GPU."""
 
     def __init__(self, mesh, device=0, channel_of_sensor=None, n_channels=None,
-                 max_leaf_size=4, sah_bins=32):
+                 max_leaf_size=4, sah_bins=32, safety_cells=0):
         self.lib = load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.mesh = mesh
@@ -84,11 +84,12 @@ class Detector:
             self.n_channels = nch
         else:
             self.n_channels = int(max(mesh.n_sensors, int(mesh.sensor.max()) + 1, 1))
-        check(self.lib.xp_build_bvh(self.ctx, ctypes.byref(BvhOptions(max_leaf_size, sah_bins))),
-              self.ctx)
+        check(self.lib.xp_build_bvh(self.ctx, ctypes.byref(
+            BvhOptions(max_leaf_size, sah_bins, safety_cells))), self.ctx)
         info = BvhInfo()
         check(self.lib.xp_bvh_stats(self.ctx, ctypes.byref(info)), self.ctx)
         self.bvh = {k: getattr(info, k) for k, _ in BvhInfo._fields_}
+        self.bvh["safety_dims"] = list(info.safety_dims)
 
     def _upload_mesh(self, mesh):
         self._mesh_arrays = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
@@ -141,7 +142,7 @@ class Detector:
 
         Returns a dict of device tensors: 'hit_map' int32 [events, channels]
         (accumulated into when passed in), and when requested 'grad' float64
-        [events, channels, 4], 'records' uint8 [n, 96], 'stats' uint64 [16]."""
+        [events, channels, 4], 'records' uint8 [n, 96], 'stats' uint64 [24]."""
         ds = self.sources(src)
         n = ds.n_photons if n_photons is None else int(n_photons)
         dev = self.device
@@ -155,7 +156,7 @@ class Detector:
         rec = torch.empty((n, RECORD_DTYPE.itemsize), dtype=torch.uint8, device=dev) if records else None
         if rec is not None:
             out["records"] = rec
-        st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
+        st = torch.zeros(24, dtype=torch.int64, device=dev) if stats else None
         if st is not None:
             out["stats"] = st
         lc = LaunchCfg(**launch) if launch else None

@@ -231,6 +231,30 @@ def test_stack_spill_to_global_does_not_change_results(rt):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("geom", ["darwin", "tpc1"])
+def test_safety_grid_does_not_change_results(rt, geom):
+    """Skipping the search where the free path ends before any triangle gives
+    exactly the search's answer: hit maps bit for bit with and without the grid."""
+    if geom == "darwin":
+        mesh = W.darwin()
+        src = W.darwin_tpc(n_photons=2_000_000, mesh=mesh).sources
+    else:
+        mesh = W.tpc1()
+        src = W.small_tpc(photons_per_point=100_000).sources
+    with_grid = rt.Detector(mesh, device=0, safety_cells=128)
+    without = rt.Detector(mesh, device=0, safety_cells=0)
+    assert min(with_grid.bvh["safety_dims"]) > 0 and without.bvh["safety_dims"] == [0, 0, 0]
+    a = with_grid.propagate(src, seed=6, stats=True)
+    b = without.propagate(src, seed=6, stats=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["hit_map"], b["hit_map"])
+    sa, sb = a["stats"].cpu().numpy(), b["stats"].cpu().numpy()
+    assert np.array_equal(sa[:10], sb[:10])  # same terminal flags and step counts
+    assert sb[14] == 0 and sa[14] > 0        # the grid skipped searches
+    if geom == "darwin":
+        assert sa[14] > 0.2 * sa[9]
+
+
 def test_darwin_parity_sampled(rt):
     """DARWIN-scale mesh: 1e6 photons uniform in the active volume; the oracle
     recomputes a sample of them one by one."""
