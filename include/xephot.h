@@ -158,8 +158,10 @@ typedef struct xp_bvh_stats {
 
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
  * it.  opts may be NULL (defaults).  Must follow xp_load_mesh
- * (else XP_ERR_STATE).  Synchronizes the device.  Errors: XP_ERR_STATE,
- * XP_ERR_INVALID_ARG, XP_ERR_OOM, XP_ERR_HIP, XP_ERR_UNSUPPORTED. */
+ * (else XP_ERR_STATE).  Meshes of 2^28 or more triangles are rejected
+ * (XP_ERR_MESH: leaf ranges are packed into 31 bits).  Synchronizes the device.
+ * Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG, XP_ERR_MESH, XP_ERR_OOM, XP_ERR_HIP,
+ * XP_ERR_UNSUPPORTED. */
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);
 int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
 

@@ -59,6 +59,14 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
     err = "empty mesh";
     return false;
   }
+  if (nt >= kMaxLeafFirst) {
+    err = "mesh has 2^28 or more triangles";
+    return false;
+  }
+  if (max_leaf < 1 || max_leaf > 8) {
+    err = "max_leaf_size must be 1..8";
+    return false;
+  }
   std::vector<Box> tb(nt);
   std::vector<float> cen(3 * nt);
   for (int64_t i = 0; i < nt; ++i) {
@@ -200,8 +208,8 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
       if (k >= nk) {
         node.lox[k] = node.loy[k] = node.loz[k] = 0.0f;
         node.hix[k] = node.hiy[k] = node.hiz[k] = 0.0f;
-        node.child[k] = 0;
-        node.count[k] = -1;
+        node.child[k] = kEmptyChild;
+        node.reserved[k] = 0;
         continue;
       }
       const Node2& c = n2[kids[k]];
@@ -215,16 +223,15 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
       }
       node.lox[k] = lo[0]; node.loy[k] = lo[1]; node.loz[k] = lo[2];
       node.hix[k] = hi[0]; node.hiy[k] = hi[1]; node.hiz[k] = hi[2];
+      node.reserved[k] = 0;
       if (is_leaf(kids[k])) {
-        node.child[k] = ~c.first;
-        node.count[k] = c.count;
+        node.child[k] = ~((c.first << 3) | (c.count - 1));
       } else {
         const int32_t slot = int32_t(out.nodes.size());
         out.nodes.emplace_back();
         level_of.push_back(it.level + 1);
         depth = std::max(depth, it.level + 1);
         node.child[k] = slot;
-        node.count[k] = 0;
         q.push_back({kids[k], slot, it.level + 1});
       }
     }
@@ -236,18 +243,18 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
   for (int l = 1; l <= depth; ++l) out.level_end[l] = std::max(out.level_end[l], out.level_end[l - 1]);
 
   // worst-case stack of the traversal: a visit pushes at most (children - 1)
-  // entries (inner nodes or leaves), one child being followed or postponed;
-  // need(node) = (children - 1) + max need(inner child)
+  // of its own children (one is followed or postponed) plus the partly tested
+  // leaf the lane may still hold; need(node) = children + max need(inner child)
   std::vector<int32_t> need(out.nodes.size(), 0);
   for (int64_t i = int64_t(out.nodes.size()) - 1; i >= 0; --i) {
     const Node4& nd = out.nodes[i];
     int kids = 0, sub = 0;
     for (int k = 0; k < 4; ++k) {
-      if (nd.count[k] < 0) continue;
+      if (nd.child[k] == kEmptyChild) continue;
       ++kids;
-      if (nd.count[k] == 0) sub = std::max(sub, need[nd.child[k]]);
+      if (nd.child[k] >= 0) sub = std::max(sub, need[nd.child[k]]);
     }
-    need[i] = std::max(0, kids - 1) + sub;
+    need[i] = kids + sub;
   }
   out.max_stack = need[0] + 1;
 

@@ -274,14 +274,14 @@ struct Counters {
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
 // from LDS, the rest from global memory.
 __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                           int32_t n_lds, int32_t node, float4 (&q)[8]) {
+                                           int32_t n_lds, int32_t node, float4 (&q)[7]) {
   if (node < n_lds) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) q[i] = lds_nodes[node * 8 + i];
+    for (int i = 0; i < 7; ++i) q[i] = lds_nodes[node * 8 + i];
   } else {
     const float4* g = reinterpret_cast<const float4*>(gnodes + node);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) q[i] = g[i];
+    for (int i = 0; i < 7; ++i) q[i] = g[i];
   }
 }
 
@@ -299,10 +299,10 @@ struct LaneStack {
   __device__ __forceinline__ bool push(int32_t e) {
     if (sp >= total) return false;
     if (sp - base > mask) {  // ring full: move the oldest entry to the overflow array
-      glob[int64_t(base) * gstride] = lds[(base & mask) * stride];
+      glob[int64_t(base) * gstride] = lds[__mul24(base & mask, stride)];
       ++base;
     }
-    lds[(sp & mask) * stride] = e;
+    lds[__mul24(sp & mask, stride)] = e;
     ++sp;
     return true;
   }
@@ -312,7 +312,7 @@ struct LaneStack {
       base = sp;
       return glob[int64_t(sp) * gstride];
     }
-    return lds[(sp & mask) * stride];
+    return lds[__mul24(sp & mask, stride)];
   }
 };
 
@@ -328,8 +328,8 @@ __device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t
 }
 
 // Visit one inner node: test its four child boxes, order the hits by entry
-// distance, follow the nearest inner child, postpone the nearest leaf (the
-// slot is free when a node is visited) and push the rest far-first.  Stack
+// distance, follow the nearest inner child, postpone the nearest leaf (a leaf
+// the lane still holds is pushed) and push the rest far-first.  Stack
 // entries are node indices (>= 0) or complemented packed leaves
 // (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
 template <bool kCount>
@@ -337,7 +337,7 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
                                            const float4* lds_nodes, int32_t n_lds, f3 inv, f3 oi,
                                            float tmax, LaneStack& st, int32_t& node,
                                            int32_t& leaf, Counters& cnt) {
-  float4 q[8];
+  float4 q[7];
   fetch_node(gnodes, lds_nodes, n_lds, node, q);
   if (kCount) cnt.nodes++;
   const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
@@ -348,8 +348,6 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
   const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
                             __float_as_int(q[6].z), __float_as_int(q[6].w)};
-  const int32_t count[4] = {__float_as_int(q[7].x), __float_as_int(q[7].y),
-                            __float_as_int(q[7].z), __float_as_int(q[7].w)};
   float key[4];
   int32_t ent[4];
 #pragma unroll
@@ -359,9 +357,9 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
     const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-    const bool hit = count[i] >= 0 && tn <= tf * 1.0000005f;
+    const bool hit = child[i] != kEmptyChild && tn <= tf * 1.0000005f;
     key[i] = hit ? tn : kInfF;
-    ent[i] = count[i] > 0 ? ~((~child[i] << 3) | (count[i] - 1)) : child[i];
+    ent[i] = child[i];
   }
   // ascending entry distance (a 5-comparator network); misses sort last
   cswap(key[0], ent[0], key[1], ent[1]);
@@ -842,6 +840,10 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
       t_mark = t_now;
       cnt.slots++;
     }
+    // A micro-step tests at most one triangle and then visits at most one node:
+    // when the wave's lanes are split between the two kinds of work it pays for
+    // both either way, so a lane holding a leaf and a node does both.  The
+    // closest hit does not depend on the order in which candidates are tested.
     if (state == kTraversing) {
       if (kCount) cnt.busy++;
       if (leaf < 0 && node < 0 && stack.sp > 0) {
@@ -854,15 +856,20 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
         if (kCount) cnt.tris++;
         test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
         leaf = rest > 0 ? (((k + 1) << 3) | (rest - 1)) : -1;
-      } else if (node >= 0) {
+      }
+      if (leaf < 0 && node < 0 && stack.sp > 0) {
+        const int32_t e = stack.pop();
+        if (e >= 0) node = e; else leaf = ~e;
+      }
+      if (node >= 0) {
         if (!visit_node<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf,
                                 cnt)) {
           b.tri = kTraversalFailed;
           state = kWaiting;
         }
-      } else {
-        state = kWaiting;  // search complete: b holds the closest hit (or none)
       }
+      // search complete: b holds the closest hit (or none)
+      if (state == kTraversing && leaf < 0 && node < 0 && stack.sp == 0) state = kWaiting;
     }
     if (kCount) cyc_search += clock64() - t_mark;
   }

@@ -21,15 +21,19 @@ constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
 
 // 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
-// reads the node with eight 16-byte loads.
-//   count[i] >  0 : leaf child, triangles [~child[i], ~child[i] + count[i])
-//   count[i] == 0 : inner child, node index child[i]
-//   count[i] <  0 : empty slot
+// reads the node with seven 16-byte loads.  child[i] is the traversal stack
+// entry of the child itself:
+//   child[i] >= 0          : inner child, node index
+//   child[i] == kEmptyChild: empty slot
+//   otherwise              : leaf child, ~(first << 3 | (count - 1)): triangle
+//                            records [first, first + count), 1 <= count <= 8
 struct alignas(128) Node4 {
   float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
   int32_t child[4];
-  int32_t count[4];
+  int32_t reserved[4];
 };
+constexpr int32_t kEmptyChild = -1 - 0x7fffffff;
+constexpr int64_t kMaxLeafFirst = int64_t(1) << 28;  // leaf ranges pack first << 3
 static_assert(sizeof(Node4) == 128, "Node4 must be one 128-byte line");
 
 // Triangle record in leaf order, three 16-byte vectors:
