@@ -147,7 +147,8 @@ typedef struct xp_bvh_options {
 
 typedef struct xp_bvh_stats {
   int64_t n_nodes;         /* 4-wide nodes of 128 bytes */
-  int64_t n_triangles;     /* 48-byte triangle records */
+  int64_t n_triangles;     /* triangles; stored as 48-byte records in three copies, one
+                              per dominant ray axis (triangle_bytes = 3 * 48 * n) */
   int32_t depth;           /* levels below the root */
   int32_t max_stack;       /* worst-case traversal stack entries */
   int64_t node_bytes, triangle_bytes;
@@ -220,7 +221,7 @@ typedef struct xp_launch_cfg {
   int32_t chunk;           /* photon ids claimed per wave refill (0 = default 64) */
   int32_t lds_levels;      /* BVH levels staged in LDS, 0..4 (-1 = default) */
   int32_t stack_lds;       /* traversal-stack entries per lane kept in LDS, a power of
-                              two in 2..64 (0 = default 16); deeper entries spill to a
+                              two in 4..64 (0 = default 16); deeper entries spill to a
                               global overflow area allocated by xp_build_bvh */
   int32_t wave_batch;      /* photons per wave interaction phase: a wave interrupts its
                               closest-hit searches to run the interactions, tallies and

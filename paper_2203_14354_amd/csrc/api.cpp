@@ -167,8 +167,8 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (lc.wave_batch == 0) lc.wave_batch = xp::kWaveBatch;
   if (lc.wave_batch < 1 || lc.wave_batch > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "wave_batch must be in 1..64");
-  if (lc.stack_lds < 2 || lc.stack_lds > 64 || (lc.stack_lds & (lc.stack_lds - 1)))
-    return fail(ctx, XP_ERR_INVALID_ARG, "stack_lds must be a power of two in 2..64");
+  if (lc.stack_lds < 4 || lc.stack_lds > 64 || (lc.stack_lds & (lc.stack_lds - 1)))
+    return fail(ctx, XP_ERR_INVALID_ARG, "stack_lds must be a power of two in 4..64");
   if (lc.block_size != 64 && lc.block_size != 128 && lc.block_size != 256)
     return fail(ctx, XP_ERR_INVALID_ARG, "block_size must be 64, 128 or 256");
   if (lc.lds_levels > 4) return fail(ctx, XP_ERR_INVALID_ARG, "lds_levels must be <= 4");
@@ -177,6 +177,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   std::memset(&a, 0, sizeof(a));
   a.nodes = ctx->d_nodes;
   a.tris = ctx->d_tris;
+  a.n_tris = int32_t(ctx->stats.n_triangles);
   a.channel_of_sensor = ctx->d_channel;
   const int levels = std::min<int>(lc.lds_levels, int(ctx->bvh.level_end.size()));
   a.n_lds_nodes = levels > 0 ? ctx->bvh.level_end[levels - 1] : 0;
@@ -505,7 +506,7 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     if (rc != XP_OK) return rc;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     ctx->stats.n_nodes = int64_t(r.nodes.size());
-    ctx->stats.n_triangles = int64_t(r.tris.size());
+    ctx->stats.n_triangles = nt;
     ctx->stats.depth = r.depth;
     ctx->stats.max_stack = r.max_stack;
     ctx->stats.node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
@@ -664,7 +665,7 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   int32_t depth_pow2 = 1;
-  while (depth_pow2 < ctx->bvh.max_stack) depth_pow2 <<= 1;
+  while (depth_pow2 < ctx->bvh.max_stack + 4) depth_pow2 <<= 1;
   const hipError_t e = xp::launch_closest_hit(
       ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_triangles), depth_pow2, n, orig, dir,
       skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));

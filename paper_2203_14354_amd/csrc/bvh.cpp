@@ -258,26 +258,29 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
   }
   out.max_stack = need[0] + 1;
 
-  // ---- triangle records in leaf order ----
-  out.tris.resize(nt);
+  // ---- triangle records in leaf order, three rotated copies ----
+  out.tris.resize(3 * nt);
   for (int64_t i = 0; i < nt; ++i) {
     const int32_t t = perm[i];
-    TriRec r;
     const float* p0 = vtx + 3 * int64_t(tri[3 * int64_t(t)]);
     const float* p1 = vtx + 3 * int64_t(tri[3 * int64_t(t) + 1]);
     const float* p2 = vtx + 3 * int64_t(tri[3 * int64_t(t) + 2]);
-    for (int k = 0; k < 3; ++k) {
-      r.a[k] = p0[k];
-      r.b[k] = p1[k];
-      r.c[k] = p2[k];
-    }
     const uint32_t packed = uint32_t(mat_in[t]) | (uint32_t(mat_out[t]) << 8) |
                             (uint32_t(surface[t] + 1) << 16);
     const int32_t sens = sensor[t];
-    std::memcpy(&r.a[3], &t, 4);
-    std::memcpy(&r.b[3], &packed, 4);
-    std::memcpy(&r.c[3], &sens, 4);
-    out.tris[i] = r;
+    for (int kz = 0; kz < 3; ++kz) {
+      TriRec r;
+      for (int k = 0; k < 3; ++k) {
+        const int src = (kz + 1 + k) % 3;  // k = 0, 1, 2 -> kx, ky, kz
+        r.a[k] = p0[src];
+        r.b[k] = p1[src];
+        r.c[k] = p2[src];
+      }
+      std::memcpy(&r.a[3], &t, 4);
+      std::memcpy(&r.b[3], &packed, 4);
+      std::memcpy(&r.c[3], &sens, 4);
+      out.tris[((kz + 1) % 3) * nt + i] = r;
+    }
   }
   return true;
 }

@@ -41,13 +41,14 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    // one 32 x 32 -> 64-bit multiply-add instruction per product
+    const uint64_t p0 = uint64_t(c0) * 0xD2511F53ull;
+    const uint64_t p1 = uint64_t(c2) * 0xCD9E8D57ull;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = uint32_t(p1);
     c2 = n2;
-    c3 = lo0;
+    c3 = uint32_t(p0);
   }
   return make_uint4(c0, c1, c2, c3);
 }
@@ -195,28 +196,30 @@ __device__ __forceinline__ bool fresnel(Photon& p, f3 nhat, float n1, float n2, 
 // ---------------------------------------------------------------------------
 // ray / triangle (watertight, Woop, Benthin and Wald, JCGT 2013), FP32
 // ---------------------------------------------------------------------------
+// The ray in the frame of its dominant axis kz: origin rotated to
+// (kx, ky, kz) = (kz + 1, kz + 2, kz) mod 3, shear constants, and the first
+// record of the triangle copy rotated the same way.  The method swaps kx and ky
+// when d_kz < 0 to keep the winding; without the swap u, v, w, the determinant
+// and the distance numerator are all exactly negated (the products are not
+// contracted), which changes neither the inside test nor the distance.
 struct RayW {
-  f3 o;
-  int kx, ky, kz;
+  f3 o;           // rotated origin
   float sx, sy, sz;
+  int32_t toff;   // record offset of the rotated triangle copy
 };
 
-__device__ __forceinline__ RayW make_ray(f3 o, f3 d) {
+__device__ __forceinline__ RayW make_ray(f3 o, f3 d, int32_t n_tris) {
   RayW r;
-  r.o = o;
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
-  r.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-  r.kx = r.kz == 2 ? 0 : r.kz + 1;
-  r.ky = r.kx == 2 ? 0 : r.kx + 1;
-  const float dz = comp(d, r.kz);
-  if (dz < 0.0f) {
-    const int t = r.kx;
-    r.kx = r.ky;
-    r.ky = t;
-  }
-  r.sx = comp(d, r.kx) / dz;
-  r.sy = comp(d, r.ky) / dz;
+  const int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  const int kx = kz == 2 ? 0 : kz + 1;
+  const int ky = kx == 2 ? 0 : kx + 1;
+  r.o = f3{comp(o, kx), comp(o, ky), comp(o, kz)};
+  const float dz = comp(d, kz);
+  r.sx = comp(d, kx) / dz;
+  r.sy = comp(d, ky) / dz;
   r.sz = 1.0f / dz;
+  r.toff = kx * n_tris;  // (kz + 1) mod 3 == kx
   return r;
 }
 
@@ -224,13 +227,14 @@ __device__ __forceinline__ RayW make_ray(f3 o, f3 d) {
 // function of a shared edge is exactly negated between its two triangles
 __device__ __forceinline__ float intersect(const RayW& r, const float* va, const float* vb,
                                            const float* vc) {
+  // vertices already rotated to (kx, ky, kz)
   const f3 a{va[0] - r.o.x, va[1] - r.o.y, va[2] - r.o.z};
   const f3 b{vb[0] - r.o.x, vb[1] - r.o.y, vb[2] - r.o.z};
   const f3 c{vc[0] - r.o.x, vc[1] - r.o.y, vc[2] - r.o.z};
-  const float akz = comp(a, r.kz), bkz = comp(b, r.kz), ckz = comp(c, r.kz);
-  const float ax = fmaf(-r.sx, akz, comp(a, r.kx)), ay = fmaf(-r.sy, akz, comp(a, r.ky));
-  const float bx = fmaf(-r.sx, bkz, comp(b, r.kx)), by = fmaf(-r.sy, bkz, comp(b, r.ky));
-  const float cx = fmaf(-r.sx, ckz, comp(c, r.kx)), cy = fmaf(-r.sy, ckz, comp(c, r.ky));
+  const float akz = a.z, bkz = b.z, ckz = c.z;
+  const float ax = fmaf(-r.sx, akz, a.x), ay = fmaf(-r.sy, akz, a.y);
+  const float bx = fmaf(-r.sx, bkz, b.x), by = fmaf(-r.sy, bkz, b.y);
+  const float cx = fmaf(-r.sx, ckz, c.x), cy = fmaf(-r.sy, ckz, c.y);
   const float u = __fsub_rn(__fmul_rn(cx, by), __fmul_rn(cy, bx));
   const float v = __fsub_rn(__fmul_rn(ax, cy), __fmul_rn(ay, cx));
   const float w = __fsub_rn(__fmul_rn(bx, ay), __fmul_rn(by, ax));
@@ -239,7 +243,7 @@ __device__ __forceinline__ float intersect(const RayW& r, const float* va, const
   if (det == 0.0f) return kInfF;
   const float az = r.sz * akz, bz = r.sz * bkz, cz = r.sz * ckz;
   const float t = __fadd_rn(__fadd_rn(__fmul_rn(u, az), __fmul_rn(v, bz)), __fmul_rn(w, cz));
-  return __fdiv_rn(t, det);
+  return t * __builtin_amdgcn_rcpf(det);  // hardware reciprocal, 1 ulp
 }
 
 struct Best {
@@ -250,9 +254,10 @@ struct Best {
 
 __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, int32_t k,
                                               const RayW& r, float tmin, int32_t skip, Best& b) {
-  const float4 A = *reinterpret_cast<const float4*>(tris[k].a);
-  const float4 B = *reinterpret_cast<const float4*>(tris[k].b);
-  const float4 C = *reinterpret_cast<const float4*>(tris[k].c);
+  const TriRec& rec = tris[r.toff + k];  // the copy rotated for this ray
+  const float4 A = *reinterpret_cast<const float4*>(rec.a);
+  const float4 B = *reinterpret_cast<const float4*>(rec.b);
+  const float4 C = *reinterpret_cast<const float4*>(rec.c);
   const int32_t id = __float_as_int(A.w);
   if (id == skip) return;
   const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
@@ -285,9 +290,11 @@ __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, con
   }
 }
 
-// Per-lane traversal stack: the newest `lds_cap` entries (a power of two) in
-// an LDS ring, older ones spilled to this lane's column of a global overflow
-// array.  `total` is the host-computed worst case; a push beyond it fails.
+// Per-lane traversal stack: the newest `lds_cap` entries (a power of two, at
+// least 4) in an LDS ring, older ones spilled to this lane's column of a
+// global overflow array.  A node visit first makes room for its (at most four)
+// pushes, then writes them without further tests.  `total` is the
+// host-computed worst case; a visit that would exceed it fails.
 struct LaneStack {
   int32_t* lds;        // this lane's first LDS slot; slot k at lds[k * stride]
   int32_t stride;
@@ -296,15 +303,16 @@ struct LaneStack {
   int64_t gstride;
   int32_t total;
   int32_t sp, base;    // entries in use; entries held in the overflow array
-  __device__ __forceinline__ bool push(int32_t e) {
-    if (sp >= total) return false;
-    if (sp - base > mask) {  // ring full: move the oldest entry to the overflow array
+  // make room for four entries in the ring (the oldest move to the overflow array)
+  __device__ __forceinline__ void reserve4() {
+    while (sp - base > mask - 3) {
       glob[int64_t(base) * gstride] = lds[__mul24(base & mask, stride)];
       ++base;
     }
-    lds[__mul24(sp & mask, stride)] = e;
-    ++sp;
-    return true;
+  }
+  // write entry j (< 4) above the top; valid after reserve4
+  __device__ __forceinline__ void put(int32_t j, int32_t e) {
+    lds[__mul24((sp + j) & mask, stride)] = e;
   }
   __device__ __forceinline__ int32_t pop() {
     --sp;
@@ -369,20 +377,25 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   cswap(key[1], ent[1], key[2], ent[2]);
   node = -1;
   constexpr int32_t kNone = -1 - 0x7fffffff;
+  st.reserve4();
+  int32_t npush = 0;
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
-    if (key[i] == kInfF) continue;
     const int32_t e = ent[i];
+    const bool hit = key[i] != kInfF;
     int32_t spill = kNone;
-    if (e < 0) {  // leaf: the nearer one keeps the slot
+    if (hit && e < 0) {  // leaf: the nearer one keeps the slot
       if (leaf >= 0) spill = ~leaf;
       leaf = ~e;
-    } else {      // inner node: the nearer one is followed
+    } else if (hit) {    // inner node: the nearer one is followed
       if (node >= 0) spill = node;
       node = e;
     }
-    if (spill != kNone && !st.push(spill)) return false;
+    st.put(npush, spill);  // a slot above the top: harmless when nothing spills
+    npush += spill != kNone ? 1 : 0;
   }
+  if (st.sp + npush > st.total) return false;
+  st.sp += npush;
   return true;
 }
 
@@ -398,9 +411,9 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
 template <bool kCount>
 __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
                                          int32_t n_lds, const TriRec* __restrict__ tris,
-                                         LaneStack st, f3 o, f3 d, float tmin, int32_t skip,
-                                         Best& b, Counters& cnt) {
-  const RayW ray = make_ray(o, d);
+                                         int32_t n_tris, LaneStack st, f3 o, f3 d, float tmin,
+                                         int32_t skip, Best& b, Counters& cnt) {
+  const RayW ray = make_ray(o, d, n_tris);
   const float tiny = 1e-30f;
   const f3 inv{1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
                1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
@@ -814,7 +827,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
       if (start) {
         sd = begin_step(p, a, pid);
         b = Best{fminf(sd.d_abs, sd.d_sca), -1, -1};
-        ray = make_ray(p.pos, p.dir);
+        ray = make_ray(p.pos, p.dir, a.n_tris);
         const float tiny = 1e-30f;
         inv = f3{1.0f / (fabsf(p.dir.x) > tiny ? p.dir.x : copysignf(tiny, p.dir.x)),
                  1.0f / (fabsf(p.dir.y) > tiny ? p.dir.y : copysignf(tiny, p.dir.y)),
@@ -915,9 +928,11 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
                                                          float tmin, float tmax, int32_t brute,
                                                          int32_t* out_tri, float* out_t) {
   extern __shared__ float4 lds[];
-  // the whole worst-case stack in LDS (stack_depth is a power of two here)
+  // the whole worst-case stack in LDS: stack_depth is a power of two of at
+  // least the bound plus the four slots a visit reserves; with the usable
+  // depth capped at stack_depth - 4 the ring never spills (no overflow array)
   LaneStack stack{reinterpret_cast<int32_t*>(lds) + threadIdx.x, int32_t(blockDim.x),
-                  stack_depth - 1, nullptr, 0, stack_depth, 0, 0};
+                  stack_depth - 1, nullptr, 0, stack_depth - 4, 0, 0};
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const f3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
@@ -927,12 +942,12 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   Counters c{0u, 0u, 0u, 0u, 0u};
   bool ok = true;
   if (brute) {
-    const RayW r = make_ray(o, d);
+    const RayW r = make_ray(o, d, n_tris);
     for (int32_t k = 0; k < n_tris; ++k) test_triangle(tris, k, r, tmin, sk, b);
   } else {
     // no node is staged (n_lds = 0); the LDS base is passed rather than a null
     // pointer, which this toolchain's inliner fails on
-    ok = traverse<false>(nodes, lds, 0, tris, stack, o, d, tmin, sk, b, c);
+    ok = traverse<false>(nodes, lds, 0, tris, n_tris, stack, o, d, tmin, sk, b, c);
   }
   out_tri[i] = ok ? b.tri : -2;
   out_t[i] = b.tri >= 0 ? b.t : kInfF;

@@ -39,6 +39,11 @@ static_assert(sizeof(Node4) == 128, "Node4 must be one 128-byte line");
 // Triangle record in leaf order, three 16-byte vectors:
 //   a = (v0, bits(mesh triangle index)), b = (v1, bits(packed media/surface)),
 //   c = (v2, bits(sensor id)); packed = mat_in | mat_out << 8 | (surface + 1) << 16.
+// The n records are stored three times, once per dominant ray axis kz, with
+// the coordinates of every vertex rotated to (kz + 1, kz + 2, kz) mod 3: the
+// copy for kz starts at record ((kz + 1) mod 3) * n, so copy 0 (kz = z) is the
+// mesh frame.  The ray/triangle test then reads the coordinates in the order
+// it uses them instead of selecting them per test.
 struct alignas(16) TriRec {
   float a[4], b[4], c[4];
 };
@@ -62,6 +67,7 @@ struct LaunchArgs {
   const Node4* nodes;
   const TriRec* tris;
   const int32_t* channel_of_sensor;
+  int32_t n_tris;          // triangles (records per rotated copy)
   int32_t n_lds_nodes;
   int32_t stack_lds;       // LDS ring entries per lane (power of two)
   int32_t stack_total;     // worst-case stack entries of the BVH
@@ -116,7 +122,7 @@ bool build_safety_grid(const float* vtx, const int32_t* tri, int64_t nt, int cel
 
 struct BvhResult {
   std::vector<Node4> nodes;
-  std::vector<TriRec> tris;
+  std::vector<TriRec> tris;        // 3 * n records: the three rotated copies
   int32_t depth = 0;
   int32_t max_stack = 0;
   std::vector<int32_t> level_end;  // level_end[l] = number of nodes in levels 0..l
