@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photons propagated/sec on DARWIN-scale TPC mesh; gradient-pass overhead vs forward"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
-NODE_BYTES, TRI_BYTES = 128, 48
+# bytes one node visit and one triangle test read: seven of the eight 16-byte
+# vectors of a 128-byte node (boxes and child entries), one 48-byte record
+NODE_BYTES, TRI_BYTES = 112, 48
 KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
                   "paper_2203_14354_amd/csrc/safety.cpp", "paper_2203_14354_amd/csrc/xp_internal.h",
                   "paper_2203_14354_amd/build.py"]
