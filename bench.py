@@ -20,6 +20,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -85,7 +87,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gradient-overhead and batched measurements")
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES bytes (a known-traffic "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -151,6 +153,7 @@ def main():
         extras.update(gradient_overhead(torch, W, Detector, dev))
         extras.update(batched_vs_plain(torch, W, Detector, dev))
         extras.update(lce_map_rate(torch, W, dev))
+        extras.update(arrival_time_and_losses(torch, W, Detector, mesh, det, dev, args.photons))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -254,6 +257,53 @@ def lce_map_rate(torch, W, dev):
                         "photons": n, "seconds": dt, "photons_per_s": n / dt,
                         "mean_lce": float(lce.mean()), "min_lce": float(lce.min()),
                         "max_lce": float(lce.max())}}
+
+
+def arrival_time_and_losses(torch, W, Detector, mesh, det, dev, n_photons):
+    """DARWIN-scale workload with the NR scintillation profile: forward with
+    the per-event arrival-time histogram (1 ns bins) and the loss table against
+    plain forward; t90 of all detected photons; the average of per-position
+    t90 over 64 point sources; the loss table folded into the paper's
+    components."""
+    from paper_2203_14354_amd import runtime
+    groups, names = W.loss_components(mesh)
+    det.set_loss_groups(groups, len(names))
+    src = W.with_scintillation(W.darwin_tpc(n_photons=n_photons, mesh=mesh).sources)
+    ds = det.sources(src)
+    n = src.n_photons
+    hm = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+    th = torch.zeros((1, 2048), dtype=torch.int32, device=dev)
+    lt = torch.zeros((len(names) + len(det.materials), 8), dtype=torch.int64, device=dev)
+    plain = lambda: det.propagate(ds, seed=5, hit_map=hm)
+    tallied = lambda: det.propagate(ds, seed=5, hit_map=hm, time_hist=th, time_bin_ns=1.0, loss=lt)
+    plain()
+    tallied()
+    dp, _ = timed_launches(plain, 3, torch)
+    dt_, _ = timed_launches(tallied, 3, torch)
+    th.zero_()
+    lt.zero_()
+    tallied()
+    t90_all = float(runtime.time_quantile(th, 1.0, 0.9)[0])
+    loss = lt.cpu().numpy().astype(np.float64) / n
+    ng = len(names)
+    absorbed = {names[g]: float(loss[g, 2] + loss[g, 3]) for g in range(ng)}
+    for m, mname in enumerate(W.DARWIN_MATERIAL_NAMES[:len(det.materials)]):
+        absorbed[mname + " (bulk)"] = float(loss[ng + m, 4])
+    # per-position t90: 64 points uniform in the active volume, 1e5 photons each
+    pts = W.uniform_points_in_cylinder(64, W.DARWIN_SRC_R, W.DARWIN_SRC_ZLO, W.DARWIN_SRC_ZHI, seed=9)
+    ps = W.with_scintillation(W.point_sources(pts, count_per_source=100_000, per_source_events=True))
+    pth = det.propagate(ps, seed=6, time_hist=2048, time_bin_ns=1.0)["time_hist"]
+    t90_pos = runtime.time_quantile(pth, 1.0, 0.9).cpu().numpy()
+    return {"arrival_time_and_losses": {
+        "workload": "darwin_tpc with the NR scintillation profile (3.5 / 24 ns, singlet 0.66), "
+                    f"{n} photons; time histogram 2048 x 1 ns; loss table by component",
+        "tallies_over_forward": statistics.median(dt_) / statistics.median(dp),
+        "photons_per_s_with_tallies": n / statistics.median(dt_),
+        "t90_all_detected_ns": t90_all,
+        "t90_mean_over_64_positions_ns": float(np.nanmean(t90_pos)),
+        "t90_min_max_over_positions_ns": [float(np.nanmin(t90_pos)), float(np.nanmax(t90_pos))],
+        "detected_fraction": float(loss[:, 1].sum()),
+        "absorbed_fraction_by_component": absorbed}}
 
 
 def cpu_baseline(W, mesh, seed, sample):

@@ -160,9 +160,9 @@ typedef struct xp_bvh_stats {
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
  * it.  opts may be NULL (defaults).  Must follow xp_load_mesh
  * (else XP_ERR_STATE).  Meshes of 2^28 or more triangles are rejected
- * (XP_ERR_MESH: leaf ranges are packed into 31 bits).  Synchronizes the device.
- * Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG, XP_ERR_MESH, XP_ERR_OOM, XP_ERR_HIP,
- * XP_ERR_UNSUPPORTED. */
+ * (XP_ERR_UNSUPPORTED: leaf ranges are packed into 31 bits).  Synchronizes the
+ * device.  Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG, XP_ERR_MESH, XP_ERR_OOM,
+ * XP_ERR_HIP, XP_ERR_UNSUPPORTED. */
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);
 int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
 
@@ -194,7 +194,18 @@ typedef struct xp_sources {
   const float* directions;    /* device: EXPLICIT float[n_photons*3] (unit) */
   const float* polarizations; /* device: EXPLICIT float[n_photons*3] (made transverse) */
   float cyl_radius, cyl_zlo, cyl_zhi; /* UNIFORM_CYLINDER */
+  int32_t time_profile;       /* XP_TIME_ZERO or XP_TIME_SCINTILLATION */
+  float tau_singlet_ns;       /* SCINTILLATION: decay constants (> 0) and the fraction */
+  float tau_triplet_ns;       /*   of photons from the singlet state (in [0, 1]); the */
+  float singlet_fraction;     /*   paper's optical table gives 3.5 ns, 24 ns, 0.66 (NR) */
 } xp_sources;
+
+/* Emission time of the photons (section "Optical properties": scintillation
+ * as a two-component exponential decay).  ZERO: every photon starts at t = 0.
+ * SCINTILLATION: photon id pid draws (u0, u1) from Philox block (step 0, sub 2);
+ * it comes from the singlet state if u0 < singlet_fraction, and starts at
+ * t = -tau ln(u1) with that state's decay constant. */
+enum { XP_TIME_ZERO = 0, XP_TIME_SCINTILLATION = 1 };
 
 /* ------------------------------------------------------------------------- */
 /* propagation                                                                */
@@ -265,6 +276,53 @@ int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp
                  int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
                  uint64_t* d_stats, const xp_launch_cfg* lc, xp_stream stream);
 
+/* Extra tallies of xp_propagate_ex (section "Light collection efficiency":
+ * arrival times and t90; section "Sources of photon losses": where photons
+ * end).  Every pointer may be NULL; buffers are caller-owned device memory
+ * and are ACCUMULATED (the caller zeroes them).
+ *   d_time_hist  int32 [n_events * n_time_bins]: detected photons by arrival
+ *                time (emission time plus time of flight); bin b holds times
+ *                in [b, b + 1) * time_bin_ns, the last bin also every later one.
+ *                Bin index = floor(time * inv) in FP32 with
+ *                inv = (float)(1.0 / time_bin_ns).
+ *   d_loss       uint64 [(n_groups + n_materials) * 8], needs
+ *                xp_set_loss_groups: photons by where they ended (row) and
+ *                terminal flag (column = flag low byte).  Photons ending on a
+ *                surface (DETECT, SENSOR_ABSORB, SURFACE_ABSORB) count in the
+ *                row of their last triangle's group; all others (BULK_ABSORB,
+ *                ESCAPED, MAX_STEPS, NAN_ABORT) in row n_groups + the material
+ *                they were in. */
+typedef struct xp_extra_tallies {
+  int32_t* d_time_hist;
+  int32_t n_time_bins;     /* >= 1 when d_time_hist is set */
+  float time_bin_ns;       /* > 0 when d_time_hist is set */
+  uint64_t* d_loss;
+} xp_extra_tallies;
+
+/* xp_propagate with the extra tallies (extra may be NULL: same as
+ * xp_propagate).  Errors as xp_propagate; XP_ERR_STATE if d_loss is set and no
+ * loss groups are. */
+int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                    int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                    uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
+                    xp_stream stream);
+
+/* Loss group of every mesh triangle (host int32 [n_triangles], mesh order,
+ * copied; values in [0, n_groups)), e.g. the detector component it belongs to.
+ * Must follow xp_load_mesh.  Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG,
+ * XP_ERR_OOM, XP_ERR_HIP. */
+int xp_set_loss_groups(xp_context* ctx, const int32_t* group_of_triangle, int32_t n_groups);
+
+/* Per-event arrival-time quantile from a time histogram (device arrays, no
+ * context): d_out[e] = the time by which a fraction q of event e's detected
+ * photons had arrived (q = 0.9: the paper's t90), interpolating linearly
+ * inside the bin where the cumulative count reaches q * total; NaN for an
+ * event with no photons, +INFINITY when the quantile falls in the last
+ * (open-ended) bin.  0 < q <= 1.  Errors: XP_ERR_INVALID_ARG, XP_ERR_HIP
+ * (xp_last_error(NULL)). */
+int xp_time_quantile(const int32_t* d_time_hist, int64_t n_events, int32_t n_time_bins,
+                     float time_bin_ns, float q, float* d_out, xp_stream stream);
+
 /* Backward pass of the expected hit map with respect to the four parameters,
  * by replaying the same photon histories (same seed and photon ids, so no
  * path storage):  d_grad_params[p] += sum over detected photons of
@@ -303,6 +361,13 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
 int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
               const float* in_pol, float cyl_radius, float cyl_zlo, float cyl_zhi, float* out_dir,
               float* out_pol, xp_stream stream);
+
+/* Emission times of photon ids pid0 .. pid0+n-1 (device float out_t[n]) and
+ * their state (out_singlet int32[n]: 1 singlet, 0 triplet; may be NULL), as
+ * xp_propagate draws them for XP_TIME_SCINTILLATION. */
+int xp_sample_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet_ns,
+                            float tau_triplet_ns, float singlet_fraction, float* out_t,
+                            int32_t* out_singlet, xp_stream stream);
 
 /* Host-only (no device needed): build the safety grid of a mesh (host arrays)
  * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,

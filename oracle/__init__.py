@@ -59,7 +59,8 @@ def lib():
                                           I32, I32]
         L.oracle_scene_destroy.argtypes = [P]
         L.oracle_run.restype = ctypes.c_int
-        L.oracle_run.argtypes = [P, I32, I32, I64, I64, P, P, I64, I32, P, P, D, D, D, U64, U64,
+        L.oracle_run.argtypes = [P, I32, I32, I64, I64, P, P, I64, I32, P, P, D, D, D, I32, D, D, D,
+                                 U64, U64,
                                  I32, D, I32, D, I64, I64, P, P, P, I32]
         L.oracle_philox.argtypes = [P, P, P]
         L.oracle_u01.restype = D
@@ -68,6 +69,7 @@ def lib():
         L.oracle_boundary.restype = I32
         L.oracle_boundary.argtypes = [I32, P, P, P, D, D, D, P, P]
         L.oracle_closest_hit.argtypes = [P, I64, P, P, D, D, P, I32, P, P]
+        L.oracle_emission_time.argtypes = [U64, U64, I64, D, D, D, P, P]
         L.oracle_max_threads.restype = I32
         _lib = L
     return _lib
@@ -155,9 +157,14 @@ def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, gr
     hm = np.zeros((s.n_events, scene.n_channels), dtype=np.int64) if hit_map else None
     gr = np.zeros((s.n_events, scene.n_channels, 4), dtype=np.float64) if grad else None
     n_src = s.n_sources if s.kind == 0 else 0
+    # the time-profile parameters enter as the FP32 values the library receives
+    tp = int(getattr(s, "time_profile", 0))
+    f32 = lambda x: float(np.float32(x))
     lib().oracle_run(scene.handle, s.kind, s.medium, s.n_photons, n_src, _p(pos), _p(offs),
                      int(s.count_per_source), 1 if s.per_source_events else 0, _p(dirs), _p(pols),
-                     float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), int(seed),
+                     float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), tp,
+                     f32(getattr(s, "tau_singlet_ns", 0.0)), f32(getattr(s, "tau_triplet_ns", 0.0)),
+                     f32(getattr(s, "singlet_fraction", 0.0)), int(seed),
                      int(pid_base), int(max_steps), float(eps), int(grad_material),
                      float(surface_offset), int(i_begin),
                      int(i_end), _p(rec), _p(hm), _p(gr), int(n_threads))
@@ -194,6 +201,75 @@ def sample(kind, seed, pid0, n, in_dir=None, in_pol=None, cyl=(0.0, 0.0, 0.0)):
     lib().oracle_sample(int(kind), int(seed), int(pid0), int(n), _p(di), _p(pi), float(cyl[0]),
                         float(cyl[1]), float(cyl[2]), _p(od), _p(op))
     return od, op
+
+
+def emission_time(seed, pid0, n, tau_singlet, tau_triplet, singlet_fraction):
+    """Scintillation emission times (ns) and states (1 singlet) of photon ids
+    pid0 .. pid0+n-1 (parameters taken as FP32 values, as the library does)."""
+    t = np.zeros(n)
+    st = np.zeros(n, dtype=np.int32)
+    f32 = lambda x: float(np.float32(x))
+    lib().oracle_emission_time(int(seed), int(pid0), int(n), f32(tau_singlet), f32(tau_triplet),
+                               f32(singlet_fraction), _p(t), _p(st))
+    return t, st
+
+
+# ---- tallies over photon records, written out from their definitions ----
+
+def time_histogram(records, n_events, n_bins, bin_ns, time_dtype=np.float64):
+    """Detected photons per event by arrival-time bin: bin floor(t / bin_ns),
+    the last bin open-ended (section "Light collection efficiency": t90 is
+    taken from the arrival times of detected photons).  With time_dtype
+    float32 the bin index is floor(t * inv) in FP32 with inv = fp32(1 / bin_ns)."""
+    det = (records["flag"] & 0xFF) == F_DETECT
+    t = records["time"][det]
+    ev = records["event"][det].astype(np.int64)
+    if time_dtype == np.float32:
+        f = t.astype(np.float32) * np.float32(1.0 / bin_ns)
+    else:
+        f = t.astype(np.float64) / bin_ns
+    b = np.where(f < n_bins - 1, np.floor(np.maximum(f, 0)), n_bins - 1).astype(np.int64)
+    h = np.zeros((n_events, n_bins), dtype=np.int64)
+    np.add.at(h, (ev, b), 1)
+    return h
+
+
+def time_quantile(hist, bin_ns, q=0.9):
+    """Per event, the time by which a fraction q of the detected photons had
+    arrived: the first bin where the cumulative count reaches q * total, with
+    linear interpolation inside it (NaN: no photons; inf: the open last bin)."""
+    hist = np.asarray(hist, dtype=np.int64)
+    out = np.full(hist.shape[0], np.nan)
+    for e in range(hist.shape[0]):
+        h = hist[e]
+        total = int(h.sum())
+        if total == 0:
+            continue
+        target = q * total
+        cum = 0
+        for b in range(len(h)):
+            c = int(h[b])
+            if c > 0 and cum + c >= target:
+                out[e] = np.inf if b == len(h) - 1 else (b + (target - cum) / c) * bin_ns
+                break
+            cum += c
+    return out
+
+
+def loss_table(records, tri_group, n_groups, n_materials):
+    """Photons by where they ended (section "Sources of photon losses", table
+    tab:graveyard): rows 0..n_groups-1 are triangle groups (photons ending on
+    a surface: detected, absorbed in a sensor, absorbed on a surface), rows
+    n_groups + m the materials (bulk absorption, escape, step limit, NaN);
+    columns are the terminal flags."""
+    fl = records["flag"] & 0xFF
+    on_surface = (fl >= F_DETECT) & (fl <= F_SURFACE_ABSORB) & (records["last_tri"] >= 0)
+    tg = np.asarray(tri_group, dtype=np.int64)
+    row = np.where(on_surface, tg[np.maximum(records["last_tri"], 0)],
+                   n_groups + records["medium"].astype(np.int64))
+    t = np.zeros((n_groups + n_materials, 8), dtype=np.int64)
+    np.add.at(t, (row, fl), 1)
+    return t
 
 
 def boundary(mode, d, e, n, n1=1.0, n2=1.0, u=0.5):

@@ -27,7 +27,12 @@
 //     (appendix item 2);
 //   * detection at photosensors: a photon reaching the photosensitive area is
 //     collected with the sensor's detection probability (the LCE definition
-//     of the Z-scan check counts photons reaching that area).
+//     of the Z-scan check counts photons reaching that area);
+//   * optionally, an emission time from the two-component exponential
+//     scintillation decay (section "Optical properties": singlet and triplet
+//     time constants and the singlet fraction), to which the time of flight
+//     (path length times n / c per medium) is added; the arrival times of
+//     detected photons give t90 (section "Light collection efficiency").
 // Where the paper is silent (random-number schedule, polarization after
 // Fresnel, the self-intersection epsilon, ...) the reading used here is the
 // one documented with the library's public header; each is restated at the
@@ -436,7 +441,16 @@ struct Sources {
   const float* directions;
   const float* polarizations;
   double cyl_radius, cyl_zlo, cyl_zhi;
+  int32_t time_profile;    // 0: t = 0 at emission; 1: scintillation decay
+  double tau_singlet, tau_triplet, singlet_fraction;
 };
+
+// Scintillation emission time: the photon comes from the singlet state with
+// probability singlet_fraction (u0 of Philox block (step 0, sub 2)), else from
+// the triplet state, and is emitted after an exponential delay with that
+// state's time constant (inverse CDF: t = -tau ln u1).
+double scintillation_time(uint64_t seed, uint64_t pid, double tau_singlet, double tau_triplet,
+                          double singlet_fraction, bool& singlet);
 
 int64_t source_of(const Sources& s, int64_t i) {
   if (s.offsets == nullptr) return i / s.count_per_source;
@@ -483,6 +497,22 @@ void emit(Photon& p, const Sources& s, int64_t i, uint64_t seed, uint64_t pid) {
     const double rr = s.cyl_radius * std::sqrt(q.u[0]);
     const double ph = 2.0 * kPi * q.u[1];
     p.pos = {rr * std::cos(ph), rr * std::sin(ph), s.cyl_zlo + (s.cyl_zhi - s.cyl_zlo) * q.u[2]};
+  }
+}
+
+double scintillation_time(uint64_t seed, uint64_t pid, double tau_singlet, double tau_triplet,
+                          double singlet_fraction, bool& singlet) {
+  const Draw r = draw(seed, pid, 0, 2);
+  singlet = r.u[0] < singlet_fraction;
+  return -(singlet ? tau_singlet : tau_triplet) * std::log(r.u[1]);
+}
+
+// Emission plus the emission time of the source's time profile.
+void emit_timed(Photon& p, const Sources& s, int64_t i, uint64_t seed, uint64_t pid) {
+  emit(p, s, i, seed, pid);
+  if (s.time_profile == 1) {
+    bool singlet;
+    p.time = scintillation_time(seed, pid, s.tau_singlet, s.tau_triplet, s.singlet_fraction, singlet);
   }
 }
 
@@ -650,13 +680,15 @@ void oracle_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
 int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int64_t n_sources,
                const float* positions, const int64_t* offsets, int64_t count_per_source,
                int32_t per_source_events, const float* directions, const float* polarizations,
-               double cyl_radius, double cyl_zlo, double cyl_zhi, uint64_t seed, uint64_t pid_base,
-               int32_t max_steps, double eps, int32_t grad_material, double surface_offset,
-               int64_t i_begin, int64_t i_end, OracleRecord* records, int64_t* hit_map,
-               double* grad, int32_t n_threads) {
+               double cyl_radius, double cyl_zlo, double cyl_zhi, int32_t time_profile,
+               double tau_singlet, double tau_triplet, double singlet_fraction, uint64_t seed,
+               uint64_t pid_base, int32_t max_steps, double eps, int32_t grad_material,
+               double surface_offset, int64_t i_begin, int64_t i_end, OracleRecord* records,
+               int64_t* hit_map, double* grad, int32_t n_threads) {
   const Scene& sc = *static_cast<Scene*>(scene);
   Sources s{kind, medium, n_photons, n_sources, positions, offsets, count_per_source,
-            per_source_events, directions, polarizations, cyl_radius, cyl_zlo, cyl_zhi};
+            per_source_events, directions, polarizations, cyl_radius, cyl_zlo, cyl_zhi,
+            time_profile, tau_singlet, tau_triplet, singlet_fraction};
   Params prm{seed, pid_base, max_steps, eps, grad_material, surface_offset};
   const Material& gm = sc.mats[grad_material >= 0 ? grad_material : 0];
 #ifdef _OPENMP
@@ -666,7 +698,7 @@ int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int
   for (int64_t i = i_begin; i < i_end; ++i) {
     const uint64_t pid = pid_base + uint64_t(i);
     Photon p{};
-    emit(p, s, i, seed, pid);
+    emit_timed(p, s, i, seed, pid);
     transport(sc, prm, pid, p);
     if (records) {
       OracleRecord& rec = records[i - i_begin];
@@ -713,6 +745,19 @@ void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
 }
 
 double oracle_u01(uint32_t x) { return u01(x); }
+
+// Scintillation emission times of photon ids pid0 .. pid0+n-1 and their state
+// (1 singlet, 0 triplet).
+void oracle_emission_time(uint64_t seed, uint64_t pid0, int64_t n, double tau_singlet,
+                          double tau_triplet, double singlet_fraction, double* out_t,
+                          int32_t* out_singlet) {
+  for (int64_t i = 0; i < n; ++i) {
+    bool singlet;
+    out_t[i] = scintillation_time(seed, pid0 + uint64_t(i), tau_singlet, tau_triplet,
+                                  singlet_fraction, singlet);
+    out_singlet[i] = singlet ? 1 : 0;
+  }
+}
 
 // kind 0: emission direction+polarization (step 0); kind 1: Lambertian about
 // in_dir (used as the normal), sub 1 of step 1; kind 2: Rayleigh from

@@ -20,6 +20,7 @@ ERRORS = {-1: "XP_ERR_INVALID_ARG", -2: "XP_ERR_STATE", -3: "XP_ERR_MESH", -4: "
 FLAG_DETECT, FLAG_SENSOR_ABSORB, FLAG_SURFACE_ABSORB, FLAG_BULK_ABSORB = 1, 2, 3, 4
 FLAG_ESCAPED, FLAG_MAX_STEPS, FLAG_NAN_ABORT, FLAG_GEOMETRY_ERROR = 5, 6, 7, 0x100
 SRC_POINTS, SRC_UNIFORM_CYLINDER, SRC_EXPLICIT = 0, 1, 2
+TIME_ZERO, TIME_SCINTILLATION = 0, 1
 
 
 class XpError(RuntimeError):
@@ -60,7 +61,14 @@ class Sources(ctypes.Structure):
                 ("count_per_source", ctypes.c_int64), ("per_source_events", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("directions", ctypes.c_void_p),
                 ("polarizations", ctypes.c_void_p), ("cyl_radius", ctypes.c_float),
-                ("cyl_zlo", ctypes.c_float), ("cyl_zhi", ctypes.c_float)]
+                ("cyl_zlo", ctypes.c_float), ("cyl_zhi", ctypes.c_float),
+                ("time_profile", ctypes.c_int32), ("tau_singlet_ns", ctypes.c_float),
+                ("tau_triplet_ns", ctypes.c_float), ("singlet_fraction", ctypes.c_float)]
+
+
+class ExtraTallies(ctypes.Structure):
+    _fields_ = [("d_time_hist", ctypes.c_void_p), ("n_time_bins", ctypes.c_int32),
+                ("time_bin_ns", ctypes.c_float), ("d_loss", ctypes.c_void_p)]
 
 
 class RunParams(ctypes.Structure):
@@ -89,8 +97,9 @@ assert RECORD_DTYPE.itemsize == 96
 # every symbol the header declares
 EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_mesh",
            "xp_set_materials", "xp_set_surfaces", "xp_set_channel_map", "xp_build_bvh",
-           "xp_bvh_stats", "xp_propagate", "xp_backward", "xp_autotune", "xp_closest_hit",
-           "xp_sample", "xp_safety_grid_host", "xp_version"]
+           "xp_bvh_stats", "xp_propagate", "xp_propagate_ex", "xp_set_loss_groups",
+           "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
+           "xp_sample_emission_time", "xp_safety_grid_host", "xp_version"]
 
 _lib = None
 
@@ -117,10 +126,14 @@ def load():
         "xp_build_bvh": (ctypes.c_int, [P, P]),
         "xp_bvh_stats": (ctypes.c_int, [P, P]),
         "xp_propagate": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
+        "xp_propagate_ex": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P]),
+        "xp_set_loss_groups": (ctypes.c_int, [P, P, I32]),
+        "xp_time_quantile": (ctypes.c_int, [P, I64, I32, F, F, P, P]),
         "xp_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
         "xp_autotune": (ctypes.c_int, [P, P, P, I64, P, P]),
         "xp_closest_hit": (ctypes.c_int, [P, I64, P, P, P, F, F, I32, P, P, P]),
         "xp_sample": (ctypes.c_int, [I32, U64, U64, I64, P, P, F, F, F, P, P, P]),
+        "xp_sample_emission_time": (ctypes.c_int, [U64, U64, I64, F, F, F, P, P, P]),
         "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
         "xp_version": (ctypes.c_char_p, []),
     }

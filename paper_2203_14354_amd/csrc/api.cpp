@@ -42,6 +42,8 @@ struct xp_context {
   xp::TriRec* d_tris = nullptr;
   int32_t* d_channel = nullptr;
   int32_t d_channel_len = 0;
+  int32_t* d_tri_group = nullptr;       // loss group per mesh triangle
+  int32_t n_groups = 0;                 // 0: no loss groups set
   unsigned long long* d_counters = nullptr;
   float* d_safety = nullptr;            // safety grid values
   xp::SafetyGrid safety;                // grid geometry (values released after upload)
@@ -159,6 +161,14 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     default:
       return fail(ctx, XP_ERR_INVALID_ARG, "unknown source kind");
   }
+  if (src->time_profile == XP_TIME_SCINTILLATION) {
+    if (!finite_pos(src->tau_singlet_ns) || !finite_pos(src->tau_triplet_ns) ||
+        !(src->singlet_fraction >= 0.0f && src->singlet_fraction <= 1.0f))
+      return fail(ctx, XP_ERR_INVALID_ARG,
+                  "scintillation profile needs decay constants > 0 and a singlet fraction in [0, 1]");
+  } else if (src->time_profile != XP_TIME_ZERO) {
+    return fail(ctx, XP_ERR_INVALID_ARG, "unknown time profile");
+  }
   lc = lc_in ? *lc_in : (ctx->tuned ? ctx->tuned_cfg : default_cfg());
   if (lc.block_size == 0) lc.block_size = 256;
   if (lc.chunk <= 0) lc.chunk = 64;
@@ -207,6 +217,10 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.cyl_r = src->cyl_radius;
   a.cyl_zlo = src->cyl_zlo;
   a.cyl_zhi = src->cyl_zhi;
+  a.time_profile = src->time_profile;
+  a.tau_singlet = src->tau_singlet_ns;
+  a.tau_triplet = src->tau_triplet_ns;
+  a.singlet_fraction = src->singlet_fraction;
   a.seed_lo = uint32_t(rp->seed);
   a.seed_hi = uint32_t(rp->seed >> 32);
   a.pid_base = rp->pid_base;
@@ -312,6 +326,7 @@ void xp_context_destroy(xp_context* ctx) {
   dfree(ctx->d_nodes);
   dfree(ctx->d_tris);
   dfree(ctx->d_channel);
+  dfree(ctx->d_tri_group);
   dfree(ctx->d_counters);
   dfree(ctx->d_stack_overflow);
   dfree(ctx->d_safety);
@@ -367,6 +382,7 @@ int xp_load_mesh(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* t
     ctx->mesh_loaded = true;
     ctx->bvh_built = false;
     ctx->tuned = false;
+    ctx->n_groups = 0;  // loss groups refer to the previous mesh
     return XP_OK;
   } catch (const std::bad_alloc&) {
     return fail(ctx, XP_ERR_OOM, "host allocation failed");
@@ -535,9 +551,10 @@ int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out) {
   return XP_OK;
 }
 
-int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp, int32_t* d_hit_map,
-                 double* d_grad, xp_photon_record* d_records, uint64_t* d_stats,
-                 const xp_launch_cfg* lc, xp_stream stream) {
+int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                    int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                    uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
+                    xp_stream stream) {
   try {
     xp::LaunchArgs a;
     xp_launch_cfg cfg;
@@ -551,11 +568,88 @@ int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp
     a.grad = d_grad;
     a.records = d_records;
     a.stats = reinterpret_cast<unsigned long long*>(d_stats);
+    if (extra && extra->d_time_hist) {
+      if (extra->n_time_bins < 1 || !finite_pos(extra->time_bin_ns))
+        return fail(ctx, XP_ERR_INVALID_ARG, "time histogram needs n_time_bins >= 1 and a bin width > 0");
+      const float inv = float(1.0 / double(extra->time_bin_ns));
+      if (!std::isfinite(inv) || !(inv > 0.0f))
+        return fail(ctx, XP_ERR_INVALID_ARG, "time bin width out of range");
+      a.time_hist = extra->d_time_hist;
+      a.n_time_bins = extra->n_time_bins;
+      a.time_inv_bin = inv;
+    }
+    if (extra && extra->d_loss) {
+      if (ctx->n_groups <= 0)
+        return fail(ctx, XP_ERR_STATE, "loss tally requested but xp_set_loss_groups has not been called");
+      a.loss = reinterpret_cast<unsigned long long*>(extra->d_loss);
+      a.tri_group = ctx->d_tri_group;
+      a.n_groups = ctx->n_groups;
+    }
     return launch(ctx, a, xp::kForward, d_grad != nullptr, d_records != nullptr, d_stats != nullptr,
                   cfg, grid, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(ctx, XP_ERR_HIP, "unexpected exception");
   }
+}
+
+int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp, int32_t* d_hit_map,
+                 double* d_grad, xp_photon_record* d_records, uint64_t* d_stats,
+                 const xp_launch_cfg* lc, xp_stream stream) {
+  return xp_propagate_ex(ctx, src, rp, d_hit_map, d_grad, d_records, d_stats, nullptr, lc, stream);
+}
+
+int xp_set_loss_groups(xp_context* ctx, const int32_t* group_of_triangle, int32_t n_groups) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
+  if (!group_of_triangle || n_groups <= 0)
+    return fail(ctx, XP_ERR_INVALID_ARG, "need a group per triangle and n_groups > 0");
+  const int64_t nt = int64_t(ctx->mat_in.size());
+  for (int64_t t = 0; t < nt; ++t)
+    if (group_of_triangle[t] < 0 || group_of_triangle[t] >= n_groups)
+      return fail(ctx, XP_ERR_INVALID_ARG, "group of triangle " + std::to_string(t) + " out of range");
+  try {
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    dfree(ctx->d_tri_group);
+    ctx->n_groups = 0;
+    hipError_t e = hipMalloc(&ctx->d_tri_group, size_t(nt) * sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(loss groups)");
+    e = hipMemcpy(ctx->d_tri_group, group_of_triangle, size_t(nt) * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(loss groups)");
+    ctx->n_groups = n_groups;
+    return XP_OK;
+  } catch (...) {
+    return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_time_quantile(const int32_t* d_time_hist, int64_t n_events, int32_t n_time_bins,
+                     float time_bin_ns, float q, float* d_out, xp_stream stream) {
+  if (n_events < 0 || (n_events > 0 && (!d_time_hist || !d_out)) || n_time_bins < 1 ||
+      !finite_pos(time_bin_ns) || !(q > 0.0f && q <= 1.0f))
+    return fail(nullptr, XP_ERR_INVALID_ARG,
+                "need histograms, n_time_bins >= 1, a bin width > 0 and 0 < q <= 1");
+  if (n_events == 0) return XP_OK;
+  const hipError_t e = xp::launch_time_quantile(d_time_hist, n_events, n_time_bins, time_bin_ns, q,
+                                                d_out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(time_quantile)");
+  return XP_OK;
+}
+
+int xp_sample_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet_ns,
+                            float tau_triplet_ns, float singlet_fraction, float* out_t,
+                            int32_t* out_singlet, xp_stream stream) {
+  if (n < 0 || (n > 0 && !out_t) || !finite_pos(tau_singlet_ns) || !finite_pos(tau_triplet_ns) ||
+      !(singlet_fraction >= 0.0f && singlet_fraction <= 1.0f))
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad emission-time sampler arguments");
+  if (n >= (int64_t(1) << 37)) return fail(nullptr, XP_ERR_INVALID_ARG, "too many samples");
+  if (n == 0) return XP_OK;
+  const hipError_t e = xp::launch_emission_time(seed, pid0, n, tau_singlet_ns, tau_triplet_ns,
+                                                singlet_fraction, out_t, out_singlet,
+                                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(emission_time)");
+  return XP_OK;
 }
 
 int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,

@@ -475,8 +475,23 @@ __device__ __forceinline__ int64_t source_of(const LaunchArgs& a, int64_t i) {
   return lo;
 }
 
+// Emission time from the two-component scintillation decay: Philox block
+// (step 0, sub 2), u0 picks the singlet state with its fraction, u1 the decay.
+__device__ __forceinline__ float emission_time(uint32_t s0, uint32_t s1, uint64_t pid,
+                                               float tau_singlet, float tau_triplet,
+                                               float singlet_fraction, bool& singlet) {
+  const R4 r = draw(s0, s1, pid, 0u, 2u);
+  singlet = r.u0 < singlet_fraction;
+  return -(singlet ? tau_singlet : tau_triplet) * logf(r.u1);
+}
+
 __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
   p.time = 0.0f;
+  if (a.time_profile == XP_TIME_SCINTILLATION) {
+    bool singlet;
+    p.time = emission_time(a.seed_lo, a.seed_hi, pid, a.tau_singlet, a.tau_triplet,
+                           a.singlet_fraction, singlet);
+  }
   p.medium = a.medium;
   p.last_tri = -1;
   p.steps = 0;
@@ -698,8 +713,11 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // ---------------------------------------------------------------------------
 enum : int32_t { kEmpty = 0, kTraversing = 1, kWaiting = 2 };
 
+// Five waves per SIMD (at most 96 VGPRs): the lane state of the search and the
+// photon fits without spilling; six or more waves force spills that cost more
+// than the extra latency hiding gains.
 template <int kMode, bool kGrad, bool kRecords, bool kCount>
-__global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
+__global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   extern __shared__ float4 lds[];
   constexpr bool kGradAcc = kGrad || kMode == kBackward;
   float4* lds_nodes = lds;
@@ -768,6 +786,13 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
             }
             if (kMode == kForward) {
               if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
+              if (a.time_hist) {
+                // arrival time bin; the last bin is open-ended (also NaN lands there)
+                const float f = p.time * a.time_inv_bin;
+                const int32_t bin = f < float(a.n_time_bins - 1) ? int32_t(fmaxf(f, 0.0f))
+                                                                 : a.n_time_bins - 1;
+                atomicAdd(a.time_hist + int64_t(p.event) * a.n_time_bins + bin, 1);
+              }
               if (kGrad && a.grad) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
@@ -777,6 +802,14 @@ __global__ void __launch_bounds__(256) propagate_kernel(const LaunchArgs a) {
 #pragma unroll
               for (int q = 0; q < 4; ++q) acc[q] += w * sc[q];
             }
+          }
+          if (kMode == kForward && a.loss) {
+            // where the photon ended: the group of its last triangle for the
+            // surface terminals, else the material it was in
+            const bool on_surface = fl >= F_DETECT && fl <= F_SURFACE_ABSORB && p.last_tri >= 0;
+            const int64_t row = on_surface ? int64_t(a.tri_group[p.last_tri])
+                                           : int64_t(a.n_groups) + p.medium;
+            atomicAdd(a.loss + row * 8 + fl, 1ull);
           }
           if (kRecords) {
             xp_photon_record& rec = a.records[idx];
@@ -953,6 +986,47 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   out_t[i] = b.tri >= 0 ? b.t : kInfF;
 }
 
+// emission times with the transport's random-number schedule (test hook)
+__global__ void emission_time_kernel(uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n,
+                                     float tau_singlet, float tau_triplet, float singlet_fraction,
+                                     float* out_t, int32_t* out_singlet) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool singlet;
+  out_t[i] = emission_time(s0, s1, pid0 + uint64_t(i), tau_singlet, tau_triplet,
+                           singlet_fraction, singlet);
+  if (out_singlet) out_singlet[i] = singlet ? 1 : 0;
+}
+
+// Quantile q of each event's arrival-time histogram: the first bin where the
+// cumulative count reaches q * total, interpolated linearly inside it.  One
+// thread per event; counts summed in 64-bit integers, the target in FP64.
+__global__ void time_quantile_kernel(const int32_t* hist, int64_t n_events, int32_t n_bins,
+                                     float bin_ns, float q, float* out) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n_events) return;
+  const int32_t* h = hist + e * n_bins;
+  int64_t total = 0;
+  for (int32_t b = 0; b < n_bins; ++b) total += h[b];
+  if (total == 0) {
+    out[e] = __builtin_nanf("");
+    return;
+  }
+  const double target = double(q) * double(total);
+  int64_t cum = 0;
+  float res = kInfF;
+  for (int32_t b = 0; b < n_bins; ++b) {
+    const int64_t c = h[b];
+    if (c > 0 && double(cum + c) >= target) {
+      res = b == n_bins - 1 ? kInfF
+                            : float((double(b) + (target - double(cum)) / double(c)) * double(bin_ns));
+      break;
+    }
+    cum += c;
+  }
+  out[e] = res;
+}
+
 // samplers with the transport's random-number schedule (test hook)
 __global__ void sample_kernel(int32_t kind, uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n,
                               const float* in_dir, const float* in_pol, float cyl_r, float zlo,
@@ -1030,6 +1104,27 @@ hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, int* out) 
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       out, reinterpret_cast<const void*>(propagate_kernel<kForward, false, false, false>), block,
       lds_bytes);
+}
+
+hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet,
+                                float tau_triplet, float singlet_fraction, float* out_t,
+                                int32_t* out_singlet, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(emission_time_kernel, dim3(uint32_t(grid)), dim3(block), 0, s,
+                     uint32_t(seed), uint32_t(seed >> 32), pid0, n, tau_singlet, tau_triplet,
+                     singlet_fraction, out_t, out_singlet);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_quantile(const int32_t* hist, int64_t n_events, int32_t n_bins,
+                                float bin_ns, float q, float* out, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n_events + block - 1) / block;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(time_quantile_kernel, dim3(uint32_t(grid)), dim3(block), 0, s, hist,
+                     n_events, n_bins, bin_ns, q, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_tris,

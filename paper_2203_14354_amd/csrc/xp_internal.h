@@ -90,6 +90,8 @@ struct LaunchArgs {
   const float* dirs;
   const float* pols;
   float cyl_r, cyl_zlo, cyl_zhi;
+  int32_t time_profile;    // XP_TIME_*
+  float tau_singlet, tau_triplet, singlet_fraction;
   // run parameters
   uint32_t seed_lo, seed_hi;
   uint64_t pid_base;
@@ -105,6 +107,12 @@ struct LaunchArgs {
   unsigned long long* work_counter;
   const float* grad_hits;  // backward: upstream gradient per hit-map cell
   double* grad_params;     // backward: 4 accumulated parameter gradients
+  int32_t* time_hist;      // [events][n_time_bins] detected photons by arrival time
+  int32_t n_time_bins;
+  float time_inv_bin;      // 1 / bin width (ns^-1), rounded once on the host
+  unsigned long long* loss;  // [n_groups + materials][8] photons by end place and flag
+  const int32_t* tri_group;  // loss group of each mesh triangle
+  int32_t n_groups;
   DevMaterial mats[kMaxMaterials];
   DevSurface surfs[kMaxSurfaces];
 };
@@ -147,5 +155,10 @@ hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_
 hipError_t launch_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,
                          const float* in_pol, float cyl_r, float zlo, float zhi, float* out_dir,
                          float* out_pol, hipStream_t s);
+hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet,
+                                float tau_triplet, float singlet_fraction, float* out_t,
+                                int32_t* out_singlet, hipStream_t s);
+hipError_t launch_time_quantile(const int32_t* hist, int64_t n_events, int32_t n_bins,
+                                float bin_ns, float q, float* out, hipStream_t s);
 
 }  // namespace xp

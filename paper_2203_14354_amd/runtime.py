@@ -13,8 +13,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RECORD_DTYPE, BvhInfo, BvhOptions, LaunchCfg, Material, RunParams, Sources,
-                   Surface, check, load)
+from ._lib import (RECORD_DTYPE, BvhInfo, BvhOptions, ExtraTallies, LaunchCfg, Material,
+                   RunParams, Sources, Surface, check, load)
 
 
 SURFACE_OFFSET = 2e-6  # m, restart distance from a surface after an interaction
@@ -60,7 +60,11 @@ class DeviceSources:
                        count_per_source=int(s.count_per_source),
                        per_source_events=1 if s.per_source_events else 0, reserved=0,
                        directions=_ptr(self.directions), polarizations=_ptr(self.polarizations),
-                       cyl_radius=s.cyl_radius, cyl_zlo=s.cyl_zlo, cyl_zhi=s.cyl_zhi)
+                       cyl_radius=s.cyl_radius, cyl_zlo=s.cyl_zlo, cyl_zhi=s.cyl_zhi,
+                       time_profile=int(getattr(s, "time_profile", 0)),
+                       tau_singlet_ns=float(getattr(s, "tau_singlet_ns", 0.0)),
+                       tau_triplet_ns=float(getattr(s, "tau_triplet_ns", 0.0)),
+                       singlet_fraction=float(getattr(s, "singlet_fraction", 0.0)))
 
 
 class Detector:
@@ -113,6 +117,13 @@ class Detector:
         check(self.lib.xp_set_surfaces(self.ctx, arr, len(surfs)), self.ctx)
         self.surfaces = list(surfs)
 
+    def set_loss_groups(self, group_of_triangle, n_groups=None):
+        """Loss group of every mesh triangle (e.g. the mesh's solid ids)."""
+        g = np.ascontiguousarray(group_of_triangle, dtype=np.int32)
+        ng = int(n_groups if n_groups is not None else g.max() + 1)
+        check(self.lib.xp_set_loss_groups(self.ctx, _host_ptr(g), ng), self.ctx)
+        self.n_groups = ng
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.xp_context_destroy(self.ctx)
@@ -137,12 +148,17 @@ class Detector:
 
     def propagate(self, src, seed=0, pid_base=0, max_steps=10_000, eps=0.0, grad_material=0,
                   hit_map: Optional[torch.Tensor] = None, grad=False, records=False, stats=False,
-                  launch: Optional[dict] = None, n_photons: Optional[int] = None, stream=None):
+                  launch: Optional[dict] = None, n_photons: Optional[int] = None, stream=None,
+                  time_hist=None, time_bin_ns: float = 1.0, loss=False):
         """Queue one transport launch on the current (or given) stream.
 
         Returns a dict of device tensors: 'hit_map' int32 [events, channels]
         (accumulated into when passed in), and when requested 'grad' float64
-        [events, channels, 4], 'records' uint8 [n, 96], 'stats' uint64 [24]."""
+        [events, channels, 4], 'records' uint8 [n, 96], 'stats' uint64 [24],
+        'time_hist' int32 [events, bins] (time_hist = number of bins of width
+        time_bin_ns, or a tensor to accumulate into) and 'loss' int64
+        [n_groups + materials, 8] (loss = True or a tensor; needs
+        set_loss_groups)."""
         ds = self.sources(src)
         n = ds.n_photons if n_photons is None else int(n_photons)
         dev = self.device
@@ -159,13 +175,33 @@ class Detector:
         st = torch.zeros(24, dtype=torch.int64, device=dev) if stats else None
         if st is not None:
             out["stats"] = st
+        th = None
+        if isinstance(time_hist, torch.Tensor):
+            th = time_hist
+        elif time_hist:
+            th = torch.zeros((ds.n_events, int(time_hist)), dtype=torch.int32, device=dev)
+        if th is not None:
+            out["time_hist"] = th
+        lt = None
+        if isinstance(loss, torch.Tensor):
+            lt = loss
+        elif loss:
+            lt = torch.zeros((getattr(self, "n_groups", 0) + len(self.materials), 8),
+                             dtype=torch.int64, device=dev)
+        if lt is not None:
+            out["loss"] = lt
+        extra = None
+        if th is not None or lt is not None:
+            extra = ExtraTallies(d_time_hist=_ptr(th), n_time_bins=th.shape[-1] if th is not None else 0,
+                                 time_bin_ns=float(time_bin_ns), d_loss=_ptr(lt))
         lc = LaunchCfg(**launch) if launch else None
         s = stream if stream is not None else current_stream(dev)
         sstruct = ds.struct(n)
         rp = self.run_params(seed, pid_base, max_steps, eps, grad_material)
-        check(self.lib.xp_propagate(self.ctx, ctypes.byref(sstruct), ctypes.byref(rp),
-                                    _ptr(hit_map), _ptr(g), _ptr(rec), _ptr(st),
-                                    ctypes.byref(lc) if lc else None, ctypes.c_void_p(s)),
+        check(self.lib.xp_propagate_ex(self.ctx, ctypes.byref(sstruct), ctypes.byref(rp),
+                                       _ptr(hit_map), _ptr(g), _ptr(rec), _ptr(st),
+                                       ctypes.byref(extra) if extra else None,
+                                       ctypes.byref(lc) if lc else None, ctypes.c_void_p(s)),
               self.ctx)
         out["_keep"] = ds
         return out
@@ -213,6 +249,32 @@ class Detector:
                                       float(tmax), 1 if brute else 0, _ptr(tri), _ptr(t),
                                       ctypes.c_void_p(s)), self.ctx)
         return tri, t
+
+
+def time_quantile(time_hist: torch.Tensor, time_bin_ns: float, q: float = 0.9, stream=None):
+    """Per-event arrival-time quantile (q = 0.9: t90) of int32 time histograms
+    [events, bins], computed on the device.  Returns float32 [events]."""
+    lib = load()
+    h = time_hist.contiguous()
+    ne, nb = (1, h.shape[0]) if h.dim() == 1 else (h.shape[0], h.shape[1])
+    out = torch.empty(ne, dtype=torch.float32, device=h.device)
+    s = stream if stream is not None else current_stream(h.device)
+    check(lib.xp_time_quantile(_ptr(h), int(ne), int(nb), float(time_bin_ns), float(q), _ptr(out),
+                               ctypes.c_void_p(s)))
+    return out
+
+
+def sample_emission_time(seed, pid0, n, tau_singlet_ns, tau_triplet_ns, singlet_fraction,
+                         device="cuda"):
+    """Device emission-time sampler with the transport's schedule (test hook)."""
+    lib = load()
+    dev = torch.device(device)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    check(lib.xp_sample_emission_time(int(seed), int(pid0), int(n), float(tau_singlet_ns),
+                                      float(tau_triplet_ns), float(singlet_fraction), _ptr(t),
+                                      _ptr(st), ctypes.c_void_p(current_stream(dev))))
+    return t, st
 
 
 def records_to_numpy(rec: torch.Tensor) -> np.ndarray:

@@ -583,6 +583,10 @@ class Sources:
     cyl_radius: float = 0.0
     cyl_zlo: float = 0.0
     cyl_zhi: float = 0.0
+    time_profile: int = 0                      # 0: t = 0; 1: scintillation decay
+    tau_singlet_ns: float = 0.0
+    tau_triplet_ns: float = 0.0
+    singlet_fraction: float = 0.0
 
     @property
     def n_sources(self) -> int:
@@ -593,6 +597,58 @@ class Sources:
     @property
     def n_events(self) -> int:
         return self.n_sources if (self.kind == SRC_POINTS and self.per_source_events) else 1
+
+
+# scintillation time profile of LXe (section "Optical properties", table
+# tab:optical): singlet / triplet time constants and the singlet fractions of
+# nuclear-recoil (NR) and electronic-recoil (ER) events
+SCINT_TAU_SINGLET_NS = 3.5
+SCINT_TAU_TRIPLET_NS = 24.0
+SINGLET_FRACTION_NR = 0.66
+SINGLET_FRACTION_ER = 0.22
+
+
+def with_scintillation(src: Sources, singlet_fraction=SINGLET_FRACTION_NR,
+                       tau_singlet_ns=SCINT_TAU_SINGLET_NS,
+                       tau_triplet_ns=SCINT_TAU_TRIPLET_NS) -> Sources:
+    """The same sources with emission times from the two-exponential decay."""
+    return dataclasses.replace(src, time_profile=1, tau_singlet_ns=float(tau_singlet_ns),
+                               tau_triplet_ns=float(tau_triplet_ns),
+                               singlet_fraction=float(singlet_fraction))
+
+
+# components of the photon-loss table (section "Sources of photon losses",
+# table tab:graveyard) in terms of the solids of the DARWIN-scale mesh
+DARWIN_LOSS_COMPONENTS = {
+    "PTFE reflectors": ("wall_liquid", "wall_gas"),
+    "array caps": ("cap_top", "cap_bottom"),
+    "LXe/GXe interface": ("interface",),
+    "top PMTs": ("window_top", "pmt_cap_top", "photocathode_top"),
+    "bottom PMTs": ("window_bottom", "pmt_cap_bottom", "photocathode_bottom"),
+    "gate": ("electrode_gate",),
+    "cathode": ("electrode_cathode",),
+    "bottom screen": ("electrode_bottom_screen",),
+}
+DARWIN_MATERIAL_NAMES = ("LXe", "GXe", "quartz")
+
+
+def loss_components(mesh: Mesh, components=None):
+    """Loss group of every triangle and the group names: the solids of the
+    mesh merged into the named components (solids not listed keep a group of
+    their own)."""
+    components = DARWIN_LOSS_COMPONENTS if components is None else components
+    names = list(components)
+    of_solid = {}
+    for g, (name, solids) in enumerate(components.items()):
+        for sname in solids:
+            if sname in mesh.solid_names:
+                of_solid[mesh.solid_names.index(sname)] = g
+    for sid, sname in enumerate(mesh.solid_names):
+        if sid not in of_solid:
+            of_solid[sid] = len(names)
+            names.append(sname)
+    lut = np.array([of_solid[i] for i in range(len(mesh.solid_names))], dtype=np.int32)
+    return lut[mesh.solid], names
 
 
 def uniform_points_in_cylinder(n, r_max, z_lo, z_hi, seed):

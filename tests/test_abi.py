@@ -46,7 +46,8 @@ def test_struct_layouts_match_header():
     from paper_2203_14354_amd import _lib
     assert ctypes.sizeof(_lib.Material) == 12
     assert ctypes.sizeof(_lib.Surface) == 28
-    assert ctypes.sizeof(_lib.Sources) == 88
+    assert ctypes.sizeof(_lib.Sources) == 104
+    assert ctypes.sizeof(_lib.ExtraTallies) == 24
     assert ctypes.sizeof(_lib.RunParams) == 32
     assert ctypes.sizeof(_lib.LaunchCfg) == 24
     assert ctypes.sizeof(_lib.BvhOptions) == 12
@@ -69,6 +70,14 @@ def test_argument_validation_without_device(lib):
     assert out.value is None
     assert len(lib.xp_last_error(None)) > 0
     assert _lib.ERRORS[-3] == "XP_ERR_MESH"
+    # extra tallies and their helpers validate before touching a device
+    assert lib.xp_set_loss_groups(None, None, 0) == -1
+    assert lib.xp_propagate_ex(None, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.xp_time_quantile(None, 1, 10, 1.0, 0.9, None, None) == -1
+    assert lib.xp_time_quantile(None, 0, 10, 1.0, 1.5, None, None) == -1  # q outside (0, 1]
+    assert lib.xp_time_quantile(None, 0, 10, 1.0, 0.9, None, None) == 0   # nothing to do
+    assert lib.xp_sample_emission_time(0, 0, 10, 3.5, 24.0, 1.5, None, None, None) == -1
+    assert lib.xp_sample_emission_time(0, 0, 0, 3.5, 24.0, 0.5, None, None, None) == 0
 
 
 def _point_triangle_distance(p, a, b, c):
