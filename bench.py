@@ -154,6 +154,7 @@ def main():
         extras.update(batched_vs_plain(torch, W, Detector, dev))
         extras.update(lce_map_rate(torch, W, dev))
         extras.update(arrival_time_and_losses(torch, W, Detector, mesh, det, dev, args.photons))
+        extras.update(design_variants(torch, W, Detector, dev))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -305,6 +306,43 @@ def arrival_time_and_losses(torch, W, Detector, mesh, det, dev, n_photons):
         "t90_min_max_over_positions_ns": [float(np.nanmin(t90_pos)), float(np.nanmax(t90_pos))],
         "detected_fraction": float(loss[:, 1].sum()),
         "absorbed_fraction_by_component": absorbed}}
+
+
+def design_variants(torch, W, Detector, dev, n=20_000_000):
+    """The paper's design variants on the same kernels: average LCE split into
+    {top, bottom, side} arrays, t90 (NR profile) and throughput, 2e7 photons
+    uniform in the active volume each."""
+    from paper_2203_14354_amd import runtime
+    out = {}
+    for name, kw in (("baseline", {}), ("coated_gate", dict(coating="gate")),
+                     ("coated_all", dict(coating="all")), ("single_phase", dict(single_phase=True)),
+                     ("no_bottom_array", dict(bottom_array=False)),
+                     ("4pi_pmt2_copper_fsr", dict(side_array="pmt2")),
+                     ("4pi_pmt2_coated_fsr", dict(side_array="pmt2", fsr="coated")),
+                     ("4pi_pmt2_no_fsr", dict(side_array="pmt2", fsr=None)),
+                     ("4pi_sipm_copper_fsr", dict(side_array="sipm"))):
+        m = W.darwin(**kw)
+        t0 = time.perf_counter()
+        det = Detector(m, device=0, channel_of_sensor=W.darwin_array_channels(m), n_channels=3)
+        build = time.perf_counter() - t0
+        src = W.with_scintillation(W.darwin_tpc(n_photons=n, mesh=m).sources)
+        ds = det.sources(src)
+        hm = torch.zeros((1, 3), dtype=torch.int32, device=dev)
+        th = torch.zeros((1, 2048), dtype=torch.int32, device=dev)
+        run = lambda: det.propagate(ds, seed=7, hit_map=hm)
+        run()
+        d, _ = timed_launches(run, 2, torch)
+        hm.zero_()
+        det.propagate(ds, seed=7, hit_map=hm, time_hist=th, time_bin_ns=1.0)
+        lce = hm.cpu().numpy()[0].astype(np.float64) / n
+        out[name] = {"triangles": int(m.n_triangles), "sensors": int(m.n_sensors),
+                     "bvh_build_s": build, "photons_per_s": n / statistics.median(d),
+                     "lce": float(lce.sum()), "lce_top_bottom_side": [float(x) for x in lce],
+                     "t90_ns": float(runtime.time_quantile(th, 1.0, 0.9)[0])}
+        det.close()
+    return {"design_variants": {"workload": f"DARWIN-scale variants, {n} photons uniform in the "
+                                            "active volume each, NR scintillation profile",
+                                "variants": out}}
 
 
 def cpu_baseline(W, mesh, seed, sample):

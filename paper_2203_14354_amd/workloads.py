@@ -314,17 +314,38 @@ DARWIN_SRC_ZHI = -0.001
 
 
 def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float = DARWIN_SEG_MAX,
-           electrodes: bool = True) -> Mesh:
-    """DARWIN-shaped dual-phase TPC (about 4.8e5 triangles)."""
+           electrodes: bool = True, coating: Optional[str] = None, single_phase: bool = False,
+           bottom_array: bool = True, side_array: Optional[str] = None,
+           fsr: Optional[str] = "copper") -> Mesh:
+    """DARWIN-shaped dual-phase TPC (about 4.8e5 triangles) and the paper's
+    design variants (section "Alternative designs"):
+      coating      "gate" or "all": electrodes covered with Al/MgF2 (90 %
+                   reflective, 85 % of it specular);
+      single_phase LXe up to the top array: no LXe/GXe interface, the gas
+                   wall and top cap become liquid PTFE;
+      bottom_array False: no bottom PMTs, the bottom PTFE reflector (0.99)
+                   in their place;
+      side_array   "pmt2" (2-inch square PMTs, 6 x 45 per plate) or "sipm"
+                   (quad SiPMs, 22 x 165 per plate) on 24 absorbing backing
+                   plates behind field-shaping rings instead of the liquid
+                   PTFE wall (the 4-pi design);
+      fsr          field-shaping rings of the 4-pi design: "copper" (45 %,
+                   specular / diffuse 3.5), "coated" (Al/MgF2, 90 %, 17) or None.
+    Sensor ids: top array, then bottom array, then the side array."""
     mb = MeshBuilder()
     LX, GX, QZ = 0, 1, 2
-    S_PTFE_L, S_PTFE_G, S_SS, S_PC, S_CAP = 0, 1, 2, 3, 4
+    S_PTFE_L, S_PTFE_G, S_SS, S_PC, S_CAP, S_COAT, S_CU, S_SIPM = 0, 1, 2, 3, 4, 5, 6, 7
     surfaces = [reflector(0.99, 0.05, grad_param=GRAD_REFLECTIVITY),
                 reflector(0.80, 0.05),
                 Surface(r_specular=0.20, r_diffuse=0.10, p_absorb=0.70),
                 Surface(p_detect=1.0, flags=SURF_DETECT_FRONT_ONLY),
-                Surface(p_absorb=1.0)]
-    # side wall: 16 bands in the liquid, one band in the gas
+                Surface(p_absorb=1.0),
+                reflector(0.90, 17.0),
+                reflector(0.45, 3.5),
+                Surface(r_specular=0.25, p_detect=0.75, flags=SURF_DETECT_FRONT_ONLY)]
+    GAS = LX if single_phase else GX
+    S_GAS_WALL = S_PTFE_L if single_phase else S_PTFE_G
+    # side wall: 16 bands in the liquid (left out by the 4-pi design), one band in the gas
     z_liq = np.linspace(DARWIN_Z_BOTCAP, DARWIN_Z_IFACE, 17)
     zs = list(z_liq) + [DARWIN_Z_TOPCAP]
     rings = [mb.add_vertices(_ring(n_wall, DARWIN_R_WALL, z)) for z in zs]
@@ -333,23 +354,28 @@ def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float
         tri = _band(rings[b], rings[b + 1])
         c = v[tri].mean(axis=1)
         gas = zs[b] >= DARWIN_Z_IFACE - 1e-12
-        mb.add_triangles(tri, c * np.array([1, 1, 0]), GX if gas else LX, GX if gas else LX,
-                         surface=S_PTFE_G if gas else S_PTFE_L,
+        if side_array and not gas:
+            continue
+        mb.add_triangles(tri, c * np.array([1, 1, 0]), GAS if gas else LX, GAS if gas else LX,
+                         surface=S_GAS_WALL if gas else S_PTFE_L,
                          solid="wall_gas" if gas else "wall_liquid")
     # end caps
     ci = mb.add_vertices([[0, 0, DARWIN_Z_BOTCAP]])[0]
     mb.add_triangles(_fan(ci, rings[0]), [0, 0, -1], LX, LX, surface=S_PTFE_L, solid="cap_bottom")
     ci = mb.add_vertices([[0, 0, DARWIN_Z_TOPCAP]])[0]
-    mb.add_triangles(_fan(ci, rings[-1]), [0, 0, 1], GX, GX, surface=S_PTFE_G, solid="cap_top")
+    mb.add_triangles(_fan(ci, rings[-1]), [0, 0, 1], GAS, GAS, surface=S_GAS_WALL, solid="cap_top")
     # liquid/gas interface, sharing the wall ring at the surface height
     iface_ring = rings[len(z_liq) - 1]
-    ci = mb.add_vertices([[0, 0, DARWIN_Z_IFACE]])[0]
-    mb.add_triangles(_fan(ci, iface_ring), [0, 0, 1], LX, GX, surface=-1, solid="interface")
+    if not single_phase:
+        ci = mb.add_vertices([[0, 0, DARWIN_Z_IFACE]])[0]
+        mb.add_triangles(_fan(ci, iface_ring), [0, 0, 1], LX, GX, surface=-1, solid="interface")
     # sensors: quartz window, photocathode on its back face, absorbing annulus and side
     centres = hex_centres(sensor_pitch, DARWIN_STRIP_RMAX - DARWIN_WINDOW_R)
     sid = 0
-    for front, toward, xe, tag in ((DARWIN_TOP_FRONT, -1.0, GX, "top"),
-                                   (DARWIN_BOT_FRONT, 1.0, LX, "bottom")):
+    arrays = [(DARWIN_TOP_FRONT, -1.0, GAS, "top")]
+    if bottom_array:
+        arrays.append((DARWIN_BOT_FRONT, 1.0, LX, "bottom"))
+    for front, toward, xe, tag in arrays:
         tv, tt, ttags = _sensor_template(front, toward, xe, QZ, S_CAP, S_PC)
         nt_s = len(tt)
         for part in ("window_", "pmt_cap_", "photocathode_"):
@@ -373,9 +399,160 @@ def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float
         for ze, pitch, tag in ((DARWIN_Z_GATE, 0.005, "gate"),
                                (DARWIN_Z_CATHODE, 0.0075, "cathode"),
                                (DARWIN_Z_BSCREEN, 0.0075, "bottom_screen")):
-            _strips(mb, ze, pitch, 0.1 * pitch, DARWIN_STRIP_RMAX, seg_max, LX, S_SS, tag)
+            coated = coating == "all" or (coating == "gate" and tag == "gate")
+            _strips(mb, ze, pitch, 0.1 * pitch, DARWIN_STRIP_RMAX, seg_max, LX,
+                    S_COAT if coated else S_SS, tag)
+    if side_array:
+        sid = _side_array(mb, n_wall, rings[0], iface_ring, side_array, fsr, sid, LX, QZ,
+                          S_CAP, S_PC, S_SIPM, {"copper": S_CU, "coated": S_COAT}.get(fsr))
     mats = [LXE, GXE, QUARTZ]
-    return mb.build(mats, surfaces, n_sensors=sid, name="darwin")
+    name = "darwin" + "".join(f"+{k}" for k, on in (
+        (f"coat-{coating}", coating), ("single-phase", single_phase),
+        ("no-bottom", not bottom_array), (f"4pi-{side_array}-fsr-{fsr}", side_array)) if on)
+    return mb.build(mats, surfaces, n_sensors=sid, name=name)
+
+
+def darwin_array_channels(mesh: Mesh) -> np.ndarray:
+    """Channel of every sensor of a DARWIN mesh: 0 top array, 1 bottom array,
+    2 side array (the paper's top / bottom / side LCE split)."""
+    ch = np.full(mesh.n_sensors, -1, dtype=np.int32)
+    names = mesh.solid_names
+    for solid, c in (("photocathode_top", 0), ("photocathode_bottom", 1),
+                     ("side_photocathode", 2), ("side_sipm", 2)):
+        if solid in names:
+            sel = (mesh.solid == names.index(solid)) & (mesh.sensor >= 0)
+            ch[mesh.sensor[sel]] = c
+    assert np.all(ch >= 0), "sensor without an array"
+    return ch
+
+
+# 4-pi design (section "4pi design"): field-shaping rings (FSRs) in the liquid,
+# 24 flat backing plates behind them carrying the side photosensors
+FSR_COUNT, FSR_STEP, FSR_HEIGHT, FSR_WIDTH = 92, 0.028, 0.020, 0.005
+SIDE_PLATES = 24
+SIDE_GAP_TO_ACTIVE = 0.0186       # FSR outer face to the sensors' active surface
+PMT2_BODY, PMT2_ACTIVE, PMT2_WINDOW_T, PMT2_GRID = 0.056, 0.0485, 0.0025, (6, 45)
+SIPM_HOLDER, SIPM_CELL, SIPM_GRID = 0.015, (0.00585, 0.00595), (22, 165)
+SENSOR_SPACING = 0.0005
+SIDE_OUTER_R = 1.340              # absorbing outer closure of the liquid annulus
+
+
+def _quads(mb, corners, outward, mat_in, mat_out, surface, sensor, solid):
+    """Add N planar quads (corners (N, 4, 3) in order around each) as two
+    triangles each, oriented toward ``outward`` (N, 3)."""
+    n = len(corners)
+    base = mb.add_vertices(corners.reshape(-1, 3))[0]
+    q = base + 4 * np.arange(n)[:, None] + np.arange(4)[None, :]
+    tri = np.concatenate([q[:, [0, 1, 2]], q[:, [0, 2, 3]]], 0)
+    out = np.concatenate([outward, outward], 0)
+    sens = np.asarray(sensor)
+    if sens.ndim:
+        sens = np.concatenate([sens, sens], 0)
+    mb.add_triangles(tri, out, mat_in, mat_out, surface=surface, sensor=sens, solid=solid)
+
+
+def _rects(centre, u, w, half_u, half_w):
+    """Corners (N, 4, 3) of rectangles centred at ``centre`` (N, 3) spanned by
+    unit vectors u, w (N, 3) with half sizes half_u, half_w."""
+    hu = half_u * u
+    hw = half_w * w
+    return np.stack([centre - hu - hw, centre + hu - hw, centre + hu + hw, centre - hu + hw], 1)
+
+
+def _side_array(mb, n_wall, bottom_ring, top_ring, kind, fsr, sid, LX, QZ, S_ABS, S_PC, S_SIPM,
+                S_FSR):
+    z_lo, z_hi = DARWIN_Z_BOTCAP, DARWIN_Z_IFACE
+    z_mid = 0.5 * (z_lo + z_hi)
+    r_in = DARWIN_R_WALL
+    # field-shaping rings: rectangular-section rings r_in .. r_in + width
+    if S_FSR is not None:
+        for k in range(FSR_COUNT):
+            zc = z_mid + (k - 0.5 * (FSR_COUNT - 1)) * FSR_STEP
+            za, zb = zc - 0.5 * FSR_HEIGHT, zc + 0.5 * FSR_HEIGHT
+            r0 = mb.add_vertices(_ring(n_wall, r_in, za))
+            r1 = mb.add_vertices(_ring(n_wall, r_in, zb))
+            r2 = mb.add_vertices(_ring(n_wall, r_in + FSR_WIDTH, za))
+            r3 = mb.add_vertices(_ring(n_wall, r_in + FSR_WIDTH, zb))
+            v = mb._vertex_array()
+            for tri, outward in ((_band(r0, r1), -1.0), (_band(r2, r3), 1.0)):
+                c = v[tri].mean(axis=1) * np.array([1, 1, 0])
+                mb.add_triangles(tri, outward * c, LX, LX, surface=S_FSR, solid="fsr")
+            mb.add_triangles(_annulus(r1, r3), [0, 0, 1], LX, LX, surface=S_FSR, solid="fsr")
+            mb.add_triangles(_annulus(r0, r2), [0, 0, -1], LX, LX, surface=S_FSR, solid="fsr")
+    # outer closure of the liquid annulus r_in .. SIDE_OUTER_R (absorbing)
+    ob = mb.add_vertices(_ring(n_wall, SIDE_OUTER_R, z_lo))
+    ot = mb.add_vertices(_ring(n_wall, SIDE_OUTER_R, z_hi))
+    v = mb._vertex_array()
+    tri = _band(ob, ot)
+    mb.add_triangles(tri, v[tri].mean(axis=1) * np.array([1, 1, 0]), LX, LX, surface=S_ABS,
+                     solid="side_closure")
+    mb.add_triangles(_annulus(bottom_ring, ob), [0, 0, -1], LX, LX, surface=S_ABS,
+                     solid="side_closure")
+    mb.add_triangles(_annulus(top_ring, ot), [0, 0, 1], LX, LX, surface=S_ABS,
+                     solid="side_closure")
+    # backing plates: a 24-gon prism 1 mm behind the active surfaces (absorbing)
+    a_active = r_in + FSR_WIDTH + SIDE_GAP_TO_ACTIVE
+    a_plate = a_active + 0.001
+    ang = 2 * np.pi * np.arange(SIDE_PLATES) / SIDE_PLATES
+    nrm = np.stack([np.cos(ang), np.sin(ang), np.zeros_like(ang)], 1)
+    tan = np.stack([-np.sin(ang), np.cos(ang), np.zeros_like(ang)], 1)
+    zax = np.broadcast_to([0.0, 0.0, 1.0], nrm.shape)
+    half_side = a_plate * math.tan(math.pi / SIDE_PLATES)
+    pc = a_plate * nrm + np.array([0, 0, z_mid])
+    _quads(mb, _rects(pc, tan, zax, half_side, 0.5 * (z_hi - z_lo)), -nrm, LX, LX, S_ABS, -1,
+           "backing_plate")
+    # sensors on each plate, centred; u along the plate, w along z
+    if kind == "pmt2":
+        pitch, (nu, nw) = PMT2_BODY + SENSOR_SPACING, PMT2_GRID
+    else:
+        pitch, (nu, nw) = SIPM_HOLDER + SENSOR_SPACING, SIPM_GRID
+    iu = (np.arange(nu) - 0.5 * (nu - 1)) * pitch
+    iw = (np.arange(nw) - 0.5 * (nw - 1)) * pitch
+    P, U, Wz = np.meshgrid(np.arange(SIDE_PLATES), iu, iw, indexing="ij")
+    P, U, Wz = P.ravel(), U.ravel(), Wz.ravel()
+    n_s = len(P)
+    n_, t_, z_ = nrm[P], tan[P], np.broadcast_to([0.0, 0.0, 1.0], (n_s, 3))
+    sensors = sid + np.arange(n_s)
+    toward = -n_  # the sensors face the axis
+    if kind == "pmt2":
+        c_act = a_active * n_ + U[:, None] * t_ + (z_mid + Wz)[:, None] * z_
+        ha, hb = 0.5 * PMT2_ACTIVE, 0.5 * PMT2_BODY
+        c_win = c_act - PMT2_WINDOW_T * n_
+        # photocathode on the back of the window: front (outer) side is the quartz
+        _quads(mb, _rects(c_act, t_, z_, ha, ha), toward, LX, QZ, S_PC, sensors, "side_photocathode")
+        # window front: a dielectric boundary, quartz inside
+        _quads(mb, _rects(c_win, t_, z_, ha, ha), toward, QZ, LX, -1, -1, "side_window")
+        # window sides: absorbing body
+        for e_dir, e_oth in ((t_, z_), (-t_, z_), (z_, t_), (-z_, t_)):
+            mid = 0.5 * (c_act + c_win) + ha * e_dir
+            _quads(mb, _rects(mid, e_oth, n_, ha, 0.5 * PMT2_WINDOW_T), e_dir, QZ, LX, S_ABS, -1,
+                   "side_body")
+        # body frame around the active area, in the plane of the photocathode
+        for e_dir, e_oth in ((t_, z_), (-t_, z_)):
+            mid = c_act + 0.5 * (ha + hb) * e_dir
+            _quads(mb, _rects(mid, e_dir, e_oth, 0.5 * (hb - ha), hb), toward, LX, LX, S_ABS, -1,
+                   "side_body")
+        for e_dir in (z_, -z_):
+            mid = c_act + 0.5 * (ha + hb) * e_dir
+            _quads(mb, _rects(mid, t_, e_dir, ha, 0.5 * (hb - ha)), toward, LX, LX, S_ABS, -1,
+                   "side_body")
+    else:
+        c_h = a_active * n_ + U[:, None] * t_ + (z_mid + Wz)[:, None] * z_
+        # ceramic holder 0.1 mm behind the cells (absorbing)
+        _quads(mb, _rects(c_h + 0.0001 * n_, t_, z_, 0.5 * SIPM_HOLDER, 0.5 * SIPM_HOLDER), toward,
+               LX, LX, S_ABS, -1, "side_holder")
+        # four cells per quad SiPM, 2 x 2 around the holder centre; the film in
+        # front of each reflects 25 % specularly, the rest reaches the active area
+        du, dw = 0.5 * SIPM_CELL[0] + 0.0002, 0.5 * SIPM_CELL[1] + 0.0002
+        cells = []
+        for su in (-1.0, 1.0):
+            for sw in (-1.0, 1.0):
+                cells.append(_rects(c_h + su * du * t_ + sw * dw * z_, t_, z_,
+                                    0.5 * SIPM_CELL[0], 0.5 * SIPM_CELL[1]))
+        corners = np.concatenate(cells, 0)
+        _quads(mb, corners, np.concatenate([toward] * 4, 0), LX, LX, S_SIPM,
+               np.concatenate([sensors] * 4, 0), "side_sipm")
+    return sid + n_s
 
 
 def _sensor_template(front, toward, xe, qz, s_cap, s_pc, nw=32):
@@ -630,6 +807,12 @@ DARWIN_LOSS_COMPONENTS = {
     "bottom screen": ("electrode_bottom_screen",),
 }
 DARWIN_MATERIAL_NAMES = ("LXe", "GXe", "quartz")
+DARWIN_LOSS_COMPONENTS_4PI = dict(
+    [(k, v) for k, v in DARWIN_LOSS_COMPONENTS.items() if k != "PTFE reflectors"]
+    + [("PTFE reflectors", ("wall_gas",)), ("FSRs", ("fsr",)),
+       ("side sensors", ("side_window", "side_body", "side_photocathode", "side_holder",
+                         "side_sipm")),
+       ("backing plates", ("backing_plate", "side_closure"))])
 
 
 def loss_components(mesh: Mesh, components=None):

@@ -1,7 +1,9 @@
-"""Invariants of the synthetic input generators (no GPU, no oracle)."""
+"""Invariants of the synthetic input generators (no GPU; the variant
+consistency check runs photons through the oracle)."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_2203_14354_amd import workloads as W
 from tests.helpers import closed_edges_ok
@@ -111,3 +113,60 @@ def test_inputs_are_seeded():
     assert np.array_equal(a, b)
     c = W.small_tpc(seed=1).sources.positions
     assert not np.array_equal(a, c)
+
+
+def test_darwin_design_variants():
+    """The paper's design variants (section "Alternative designs") on the same
+    generator: what changes and what does not."""
+    base = W.darwin()
+    # reflective coatings: only the electrode surfaces change
+    for coat, solids in (("gate", ["electrode_gate"]),
+                         ("all", ["electrode_gate", "electrode_cathode", "electrode_bottom_screen"])):
+        m = W.darwin(coating=coat)
+        assert np.array_equal(m.triangles, base.triangles)
+        changed = m.surface != base.surface
+        assert np.array_equal(changed, _sel(m, *solids))
+        s = m.surfaces[m.surface[changed][0]]
+        assert s.r_specular + s.r_diffuse == pytest.approx(0.90)
+        assert s.r_specular == pytest.approx(0.85)
+    # single phase: no gas anywhere, no interface, the gas wall becomes liquid PTFE
+    m = W.darwin(single_phase=True)
+    assert not np.any(m.mat_inner == 1) and not np.any(m.mat_outer == 1)
+    assert "interface" not in m.solid_names
+    assert m.n_triangles == base.n_triangles - 256
+    # no bottom array: the bottom PTFE (0.99) stays, 889 sensors remain
+    m = W.darwin(bottom_array=False)
+    assert m.n_sensors == 889 and "photocathode_bottom" not in m.solid_names
+    assert np.bincount(W.darwin_array_channels(m)).tolist() == [889]
+    # 4-pi: 6,480 square PMTs or 87,120 quad SiPMs on 24 plates behind 92 FSRs
+    for kind, n_side, fsr in (("pmt2", 6480, "copper"), ("pmt2", 6480, None), ("sipm", 87120, "coated")):
+        m = W.darwin(side_array=kind, fsr=fsr)
+        assert np.bincount(W.darwin_array_channels(m)).tolist() == [889, 889, n_side]
+        assert "wall_liquid" not in m.solid_names
+        n_fsr = int(_sel(m, "fsr").sum()) if "fsr" in m.solid_names else 0
+        assert n_fsr == (92 * 4 * 2 * 256 if fsr else 0)
+        # the side sensors sit between the rings and the plates, facing the axis
+        side = _sel(m, "side_photocathode" if kind == "pmt2" else "side_sipm")
+        c = m.vertices[m.triangles[side]].mean(axis=1)
+        r = np.hypot(c[:, 0], c[:, 1])
+        assert r.min() > W.DARWIN_R_WALL + W.FSR_WIDTH and r.max() < W.SIDE_OUTER_R
+        assert np.all(np.einsum("ij,ij->i", m.normals()[side], c * [1, 1, 0]) < 0)
+        assert np.all((c[:, 2] > W.DARWIN_Z_BOTCAP) & (c[:, 2] < W.DARWIN_Z_IFACE))
+    assert closed_edges_ok(W.darwin(side_array="pmt2").triangles[
+        _sel(W.darwin(side_array="pmt2"), "fsr")])
+
+
+@pytest.mark.parametrize("kw", [dict(coating="all"), dict(single_phase=True),
+                                dict(bottom_array=False), dict(side_array="pmt2"),
+                                dict(side_array="sipm", fsr=None)])
+def test_darwin_variants_are_consistent_meshes(kw):
+    """Photons through each variant (oracle, 3,000 photons): every one ends
+    with a valid terminal flag, none escapes the closed detector and none
+    meets a triangle whose media disagree with the tracked one."""
+    import oracle
+    m = W.darwin(**kw)
+    sc = oracle.Scene(m, channel_of_sensor=W.darwin_array_channels(m), n_channels=3, use_bvh=True)
+    rec = oracle.run(sc, W.darwin_tpc(n_photons=3000, mesh=m).sources, seed=3)["records"]
+    fl = rec["flag"] & 0xFF
+    assert np.all((fl >= 1) & (fl <= 4))
+    assert not np.any(rec["flag"] & oracle.F_GEOMETRY_ERROR)
