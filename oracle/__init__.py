@@ -27,9 +27,9 @@ RECORD_DTYPE = np.dtype([
     ("event", np.int32), ("medium", np.int32), ("n_scatter", np.int32), ("pad", np.int32),
     ("pos", np.float64, 3), ("dir", np.float64, 3), ("pol", np.float64, 3),
     ("time", np.float64), ("path_len", np.float64), ("sum_inv_r", np.float64),
-    ("sum_inv_t", np.float64),
+    ("sum_inv_t", np.float64), ("wavelength", np.float64),
 ])
-assert RECORD_DTYPE.itemsize == 32 + 9 * 8 + 4 * 8
+assert RECORD_DTYPE.itemsize == 32 + 9 * 8 + 5 * 8
 
 
 def build(force: bool = True) -> str:
@@ -55,12 +55,13 @@ def lib():
         P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                ctypes.c_double)
         L.oracle_scene_create.restype = P
-        L.oracle_scene_create.argtypes = [P, I64, P, I64, P, P, P, P, P, I32, P, P, I32, P, I32,
-                                          I32, I32]
+        L.oracle_scene_create.argtypes = [P, I64, P, I64, P, P, P, P, P, I32, P, P, P, I32, P,
+                                          I32, I32, I32]
+        L.oracle_scene_set_dispersion.argtypes = [P, I32, I32, P, P, P, P]
         L.oracle_scene_destroy.argtypes = [P]
         L.oracle_run.restype = ctypes.c_int
         L.oracle_run.argtypes = [P, I32, I32, I64, I64, P, P, I64, I32, P, P, D, D, D, I32, D, D, D,
-                                 U64, U64,
+                                 D, D, U64, U64,
                                  I32, D, I32, D, I64, I64, P, P, P, I32]
         L.oracle_philox.argtypes = [P, P, P]
         L.oracle_u01.restype = D
@@ -70,6 +71,9 @@ def lib():
         L.oracle_boundary.argtypes = [I32, P, P, P, D, D, D, P, P]
         L.oracle_closest_hit.argtypes = [P, I64, P, P, D, D, P, I32, P, P]
         L.oracle_emission_time.argtypes = [U64, U64, I64, D, D, D, P, P]
+        L.oracle_wavelength.argtypes = [U64, U64, I64, D, D, P]
+        L.oracle_surface_reflectance.argtypes = [I32, D, D, D, D, D, D, I64, P, P, P]
+        L.oracle_material_at.argtypes = [P, I32, I64, P, P]
         L.oracle_max_threads.restype = I32
         _lib = L
     return _lib
@@ -97,8 +101,8 @@ class Scene:
         mi, mo = keep(mesh.mat_inner, np.int32), keep(mesh.mat_outer, np.int32)
         su, se = keep(mesh.surface, np.int32), keep(mesh.sensor, np.int32)
         mats = keep(materials_array(mesh.materials), np.float32)
-        sp, stags = surfaces_array(mesh.surfaces)
-        sp, stags = keep(sp, np.float32), keep(stags, np.int32)
+        sp, stags, sopt = surfaces_array(mesh.surfaces)
+        sp, stags, sopt = keep(sp, np.float32), keep(stags, np.int32), keep(sopt, np.float32)
         if channel_of_sensor is None:
             ch = keep(np.arange(mesh.n_sensors, dtype=np.int32), np.int32)
             nch = mesh.n_sensors
@@ -108,7 +112,22 @@ class Scene:
         self.n_channels = nch
         self.handle = lib().oracle_scene_create(
             _p(v), len(v), _p(t), len(t), _p(mi), _p(mo), _p(su), _p(se), _p(mats), len(mats),
-            _p(sp), _p(stags), len(sp), _p(ch), mesh.n_sensors, nch, 1 if use_bvh else 0)
+            _p(sp), _p(stags), _p(sopt), len(sp), _p(ch), mesh.n_sensors, nch,
+            1 if use_bvh else 0)
+        for m, mat in enumerate(mesh.materials):
+            tab = getattr(mat, "dispersion", None)
+            if tab is not None:
+                tab = keep(np.asarray(tab, dtype=np.float32).reshape(-1, 4).T.copy(), np.float32)
+                lib().oracle_scene_set_dispersion(self.handle, m, tab.shape[1], _p(tab[0]),
+                                                  _p(tab[1]), _p(tab[2]), _p(tab[3]))
+
+    def material_at(self, m, lambdas):
+        """(index, absorption length, Rayleigh length) of material m at the
+        given wavelengths (nm), from its dispersion table."""
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64).reshape(-1)
+        out = np.zeros((len(lam), 3))
+        lib().oracle_material_at(self.handle, int(m), len(lam), _p(lam), _p(out))
+        return out
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -164,7 +183,9 @@ def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, gr
                      int(s.count_per_source), 1 if s.per_source_events else 0, _p(dirs), _p(pols),
                      float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), tp,
                      f32(getattr(s, "tau_singlet_ns", 0.0)), f32(getattr(s, "tau_triplet_ns", 0.0)),
-                     f32(getattr(s, "singlet_fraction", 0.0)), int(seed),
+                     f32(getattr(s, "singlet_fraction", 0.0)),
+                     f32(getattr(s, "wavelength_nm", 0.0)), f32(getattr(s, "wavelength_fwhm_nm", 0.0)),
+                     int(seed),
                      int(pid_base), int(max_steps), float(eps), int(grad_material),
                      float(surface_offset), int(i_begin),
                      int(i_end), _p(rec), _p(hm), _p(gr), int(n_threads))
@@ -212,6 +233,24 @@ def emission_time(seed, pid0, n, tau_singlet, tau_triplet, singlet_fraction):
     lib().oracle_emission_time(int(seed), int(pid0), int(n), f32(tau_singlet), f32(tau_triplet),
                                f32(singlet_fraction), _p(t), _p(st))
     return t, st
+
+
+def wavelength(seed, pid0, n, mean, fwhm):
+    """Emission wavelengths (nm) of photon ids pid0 .. pid0+n-1 (parameters as FP32)."""
+    out = np.zeros(n)
+    lib().oracle_wavelength(int(seed), int(pid0), int(n), float(np.float32(mean)),
+                            float(np.float32(fwhm)), _p(out))
+    return out
+
+
+def surface_reflectance(model, n1, n_re, n_im, film_n=0.0, film_d_nm=0.0, lam=174.8, cos_i=1.0):
+    """|r_s|^2 and |r_p|^2 of a complex-index (model 1) or thin-film (model 2)
+    surface at the given incidence cosines."""
+    c = np.ascontiguousarray(np.atleast_1d(cos_i), dtype=np.float64)
+    rs, rp = np.zeros(len(c)), np.zeros(len(c))
+    lib().oracle_surface_reflectance(int(model), float(n1), float(n_re), float(n_im), float(film_n),
+                                     float(film_d_nm), float(lam), len(c), _p(c), _p(rs), _p(rp))
+    return rs, rp
 
 
 # ---- tallies over photon records, written out from their definitions ----

@@ -32,7 +32,13 @@
 //     scintillation decay (section "Optical properties": singlet and triplet
 //     time constants and the singlet fraction), to which the time of flight
 //     (path length times n / c per medium) is added; the arrival times of
-//     detected photons give t90 (section "Light collection efficiency").
+//     detected photons give t90 (section "Light collection efficiency");
+//   * optionally, a wavelength per photon from the Gaussian emission spectrum
+//     (section "Optical properties": mean and FWHM), material properties
+//     interpolated in wavelength, and surfaces whose reflectance follows from
+//     a complex refractive index or a thin dielectric film on such a
+//     substrate (the silicon backing plates and Al/MgF2 coatings of section
+//     "Alternative designs").
 // Where the paper is silent (random-number schedule, polarization after
 // Fresnel, the self-intersection epsilon, ...) the reading used here is the
 // one documented with the library's public header; each is restated at the
@@ -41,6 +47,7 @@
 // Build: g++ -O2 -std=c++17 -fopenmp -ffp-contract=off -shared -fPIC
 
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <cstdio>
@@ -152,8 +159,13 @@ V3 random_polarization(V3 d, double u) {
 struct Surface {
   double p_detect, p_absorb, r_diffuse, r_specular, p_transmit;
   int32_t grad_param, flags;
+  int32_t model;                 // 0 explicit partition, 1 complex index, 2 thin film
+  double n_re, n_im;             // substrate index n + i k (models 1 and 2)
+  double film_n, film_d_nm;      // film index and thickness (model 2)
 };
 struct Material { double n, abs_length, rayleigh_length; };
+// one sample of a material's dispersion table
+struct DispPoint { double lambda_nm, n, abs_length, rayleigh_length; };
 
 struct BNode { double lo[3], hi[3]; int32_t left, right, first, count; };
 
@@ -161,6 +173,7 @@ struct Scene {
   std::vector<V3> v0, v1, v2;       // triangle vertices (double copies of the float inputs)
   std::vector<int32_t> mat_in, mat_out, surf, sensor;
   std::vector<Material> mats;
+  std::vector<std::vector<DispPoint>> disp;  // per material; empty: no wavelength dependence
   std::vector<Surface> surfs;
   std::vector<int32_t> channel;    // sensor -> hit-map column
   int32_t n_channels = 0;
@@ -338,6 +351,7 @@ void build_bvh(Scene& sc) {
 struct Photon {
   V3 pos, dir, pol;
   double time;
+  double wavelength;    // nm
   int32_t medium, last_tri, steps, flag, event, sensor;
   double path_len;      // path length inside the material bound to gradient params 0/1
   int32_t n_scatter;    // Rayleigh scatters in that material
@@ -427,6 +441,94 @@ bool fresnel(Photon& p, V3 nhat, double n1, double n2, double u) {
 }
 
 // ---------------------------------------------------------------------------
+// wavelength dependence
+// ---------------------------------------------------------------------------
+
+// Material properties at wavelength lambda from its dispersion table: the
+// refractive index and the attenuation coefficients 1/L (so that an infinite
+// length is a zero coefficient) are interpolated linearly between the two
+// neighbouring samples and held constant beyond the first and last.
+Material material_at(const Scene& sc, int32_t m, double lambda) {
+  const std::vector<DispPoint>& t = sc.disp[m];
+  if (t.empty()) return sc.mats[m];
+  auto inv = [](double L) { return std::isinf(L) ? 0.0 : 1.0 / L; };
+  auto len = [](double mu) { return mu > 0.0 ? 1.0 / mu : kInf; };
+  if (lambda <= t.front().lambda_nm)
+    return Material{t.front().n, t.front().abs_length, t.front().rayleigh_length};
+  if (lambda >= t.back().lambda_nm)
+    return Material{t.back().n, t.back().abs_length, t.back().rayleigh_length};
+  size_t i = 0;
+  while (t[i + 1].lambda_nm < lambda) ++i;
+  const DispPoint& a = t[i];
+  const DispPoint& b = t[i + 1];
+  const double w = (lambda - a.lambda_nm) / (b.lambda_nm - a.lambda_nm);
+  return Material{a.n + w * (b.n - a.n),
+                  len(inv(a.abs_length) + w * (inv(b.abs_length) - inv(a.abs_length))),
+                  len(inv(a.rayleigh_length) + w * (inv(b.rayleigh_length) - inv(a.rayleigh_length)))};
+}
+
+using C = std::complex<double>;
+
+// Amplitude reflection coefficients (s, p) for light arriving from a medium of
+// real index n1 at incidence cosine ci on (model 1) a medium of complex index
+// n2 = n + i k, or (model 2) a film of real index nf and thickness d on that
+// medium, at vacuum wavelength lambda.  With q_j = sqrt(n_j^2 - n1^2 sin^2)
+// (= n_j cos(theta_j), principal branch, so waves decay into absorbing or
+// evanescent layers), the interface coefficients are
+//   r_s = (q_a - q_b) / (q_a + q_b),  r_p = (n_b^2 q_a - n_a^2 q_b) / (n_b^2 q_a + n_a^2 q_b)
+// (the Born & Wolf convention of the dielectric case), and a film combines
+// its two interfaces with the phase beta = 2 pi d q_f / lambda:
+//   r = (r_01 + r_12 e^{2 i beta}) / (1 + r_01 r_12 e^{2 i beta}).
+void film_reflection(int32_t model, double n1, double ci, double n_re, double n_im, double nf,
+                     double d_nm, double lambda, C& rs, C& rp) {
+  const C n2(n_re, n_im);
+  const double s2 = n1 * n1 * (1.0 - ci * ci);  // n1^2 sin^2(theta_i)
+  const C q1(n1 * ci, 0.0);
+  const C q2 = std::sqrt(n2 * n2 - s2);
+  const C e1(n1 * n1, 0.0), e2 = n2 * n2;
+  if (model == 1) {
+    rs = (q1 - q2) / (q1 + q2);
+    rp = (e2 * q1 - e1 * q2) / (e2 * q1 + e1 * q2);
+    return;
+  }
+  const C ef(nf * nf, 0.0);
+  const C qf = std::sqrt(ef - s2);
+  const C r01s = (q1 - qf) / (q1 + qf), r12s = (qf - q2) / (qf + q2);
+  const C r01p = (ef * q1 - e1 * qf) / (ef * q1 + e1 * qf);
+  const C r12p = (e2 * qf - ef * q2) / (e2 * qf + ef * q2);
+  const C ph = std::exp(C(0.0, 2.0) * (2.0 * kPi * d_nm / lambda) * qf);
+  rs = (r01s + r12s * ph) / (1.0 + r01s * r12s * ph);
+  rp = (r01p + r12p * ph) / (1.0 + r01p * r12p * ph);
+}
+
+// Reflection off a surface of model 1 or 2: the photon is reflected
+// specularly with probability R = a_s^2 |r_s|^2 + a_p^2 |r_p|^2 (a_s, a_p:
+// components of its linear polarization along s and p; at normal incidence s
+// is taken along the polarization).  The reflected photon stays linearly
+// polarized, its s and p components scaled by |r| with the sign of Re r (the
+// real, dielectric limit).  Returns true if reflected.
+bool model_reflection(Photon& p, V3 nhat, double n1, const Surface& s, double u) {
+  const V3 d = p.dir, e = p.pol;
+  const double ci = -dot(d, nhat);
+  C rs, rp;
+  film_reflection(s.model, n1, ci, s.n_re, s.n_im, s.film_n, s.film_d_nm, p.wavelength, rs, rp);
+  V3 sv = cross(d, nhat);
+  const double sl = norm(sv);
+  const V3 sd = (sl < 1e-6) ? e : (1.0 / sl) * sv;
+  const double as = dot(e, sd);
+  const double ap = dot(e, cross(sd, d));
+  const double Rs = std::norm(rs), Rp = std::norm(rp);
+  const double R = as * as * Rs + ap * ap * Rp;
+  if (!(u < R)) return false;
+  const V3 dr = normalize(d + (2.0 * ci) * nhat);
+  const double ms = std::copysign(std::abs(rs), rs.real());
+  const double mp = std::copysign(std::abs(rp), rp.real());
+  p.pol = normalize((ms * as) * sd + (mp * ap) * cross(sd, dr));
+  p.dir = dr;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // sources
 // ---------------------------------------------------------------------------
 struct Sources {
@@ -443,7 +545,17 @@ struct Sources {
   double cyl_radius, cyl_zlo, cyl_zhi;
   int32_t time_profile;    // 0: t = 0 at emission; 1: scintillation decay
   double tau_singlet, tau_triplet, singlet_fraction;
+  double wavelength_nm, wavelength_fwhm_nm;  // Gaussian spectrum (FWHM 0: one line)
 };
+
+// Wavelength from the Gaussian emission spectrum: Philox block (step 0,
+// sub 3), Box-Muller with sigma = FWHM / (2 sqrt(2 ln 2)).
+double emission_wavelength(uint64_t seed, uint64_t pid, double mean, double fwhm) {
+  if (!(fwhm > 0.0)) return mean;
+  const Draw r = draw(seed, pid, 0, 3);
+  const double sigma = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  return mean + sigma * std::sqrt(-2.0 * std::log(r.u[0])) * std::cos(2.0 * kPi * r.u[1]);
+}
 
 // Scintillation emission time: the photon comes from the singlet state with
 // probability singlet_fraction (u0 of Philox block (step 0, sub 2)), else from
@@ -510,6 +622,7 @@ double scintillation_time(uint64_t seed, uint64_t pid, double tau_singlet, doubl
 // Emission plus the emission time of the source's time profile.
 void emit_timed(Photon& p, const Sources& s, int64_t i, uint64_t seed, uint64_t pid) {
   emit(p, s, i, seed, pid);
+  p.wavelength = emission_wavelength(seed, pid, s.wavelength_nm, s.wavelength_fwhm_nm);
   if (s.time_profile == 1) {
     bool singlet;
     p.time = scintillation_time(seed, pid, s.tau_singlet, s.tau_triplet, s.singlet_fraction, singlet);
@@ -540,7 +653,7 @@ inline double free_path(double length, double u) {
 void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
   for (int32_t step = 1; step <= prm.max_steps; ++step) {
     p.steps = step;
-    const Material& m = sc.mats[p.medium];
+    const Material m = material_at(sc, p.medium, p.wavelength);
     const Draw r = draw(prm.seed, pid, uint32_t(step), 0);
     const double d_abs = free_path(m.abs_length, r.u[0]);
     const double d_sca = free_path(m.rayleigh_length, r.u[1]);
@@ -576,6 +689,20 @@ void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
           return;
         }
         const double u = r.u[2];
+        if (s.model != 0) {
+          // reflectance from the complex index / film; the rest enters the
+          // surface's material: detected on a sensor, absorbed elsewhere
+          if (model_reflection(p, n_back, material_at(sc, m_from, p.wavelength).n, s, u)) {
+            p.pos = p.pos + prm.surface_offset * n_back;
+            p.last_tri = k;
+            if (!finite3(p.pos) || !finite3(p.dir) || !finite3(p.pol)) { p.flag |= F_NAN_ABORT; return; }
+            continue;
+          }
+          if (is_sensor) { p.flag |= F_DETECT; p.sensor = sc.sensor[k]; }
+          else p.flag |= F_SURFACE_ABSORB;
+          p.last_tri = k;
+          return;
+        }
         double c = s.p_detect;
         if (u < c) {
           if (is_sensor) { p.flag |= F_DETECT; p.sensor = sc.sensor[k]; }
@@ -611,7 +738,8 @@ void transport(const Scene& sc, const Params& prm, uint64_t pid, Photon& p) {
         }
         p.pos = p.pos + (through ? -prm.surface_offset : prm.surface_offset) * n_back;
       } else {
-        const double n1 = sc.mats[m_from].n, n2 = sc.mats[m_to].n;
+        const double n1 = material_at(sc, m_from, p.wavelength).n;
+        const double n2 = material_at(sc, m_to, p.wavelength).n;
         bool through = true;
         if (n1 != n2) through = fresnel(p, n_back, n1, n2, r.u[2]);
         if (through) p.medium = m_to;
@@ -636,12 +764,14 @@ struct OracleRecord {  // one per photon
   int32_t event, medium, n_scatter, pad;
   double pos[3], dir[3], pol[3];
   double time, path_len, sum_inv_r, sum_inv_t;
+  double wavelength;
 };
 
 void* oracle_scene_create(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
                           const int32_t* mat_in, const int32_t* mat_out, const int32_t* surf,
                           const int32_t* sensor, const float* mats, int32_t n_mats,
-                          const float* surf_p, const int32_t* surf_tags, int32_t n_surfs,
+                          const float* surf_p, const int32_t* surf_tags,
+                          const float* surf_optics, int32_t n_surfs,
                           const int32_t* channel_of_sensor, int32_t n_sensors, int32_t n_channels,
                           int32_t use_bvh) {
   Scene* sc = new Scene();
@@ -658,9 +788,12 @@ void* oracle_scene_create(const float* vtx, int64_t nv, const int32_t* tri, int6
   sc->sensor.assign(sensor, sensor + nt);
   for (int32_t i = 0; i < n_mats; ++i)
     sc->mats.push_back(Material{mats[3 * i], mats[3 * i + 1], mats[3 * i + 2]});
+  sc->disp.assign(sc->mats.size(), {});
   for (int32_t i = 0; i < n_surfs; ++i) {
     const float* q = surf_p + 5 * i;
-    sc->surfs.push_back(Surface{q[0], q[1], q[2], q[3], q[4], surf_tags[2 * i], surf_tags[2 * i + 1]});
+    const float* o = surf_optics + 4 * i;
+    sc->surfs.push_back(Surface{q[0], q[1], q[2], q[3], q[4], surf_tags[3 * i], surf_tags[3 * i + 1],
+                                surf_tags[3 * i + 2], o[0], o[1], o[2], o[3]});
   }
   sc->n_sensors = n_sensors;
   sc->n_channels = n_channels;
@@ -673,6 +806,16 @@ void* oracle_scene_create(const float* vtx, int64_t nv, const int32_t* tri, int6
 
 void oracle_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
 
+// Dispersion table of material m: n samples (lambda ascending); n = 0 removes it.
+void oracle_scene_set_dispersion(void* scene, int32_t m, int32_t n, const float* lambda_nm,
+                                 const float* index, const float* abs_length,
+                                 const float* rayleigh_length) {
+  Scene& sc = *static_cast<Scene*>(scene);
+  sc.disp[m].clear();
+  for (int32_t i = 0; i < n; ++i)
+    sc.disp[m].push_back(DispPoint{lambda_nm[i], index[i], abs_length[i], rayleigh_length[i]});
+}
+
 // Propagate photons with launch-local indices [i_begin, i_end) (photon id =
 // pid_base + i).  Optional outputs: one record per photon (indexed i - i_begin),
 // the hit map [event][channel] (int64, accumulated) and the gradient tallies
@@ -681,14 +824,16 @@ int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int
                const float* positions, const int64_t* offsets, int64_t count_per_source,
                int32_t per_source_events, const float* directions, const float* polarizations,
                double cyl_radius, double cyl_zlo, double cyl_zhi, int32_t time_profile,
-               double tau_singlet, double tau_triplet, double singlet_fraction, uint64_t seed,
+               double tau_singlet, double tau_triplet, double singlet_fraction,
+               double wavelength_nm, double wavelength_fwhm_nm, uint64_t seed,
                uint64_t pid_base, int32_t max_steps, double eps, int32_t grad_material,
                double surface_offset, int64_t i_begin, int64_t i_end, OracleRecord* records,
                int64_t* hit_map, double* grad, int32_t n_threads) {
   const Scene& sc = *static_cast<Scene*>(scene);
   Sources s{kind, medium, n_photons, n_sources, positions, offsets, count_per_source,
             per_source_events, directions, polarizations, cyl_radius, cyl_zlo, cyl_zhi,
-            time_profile, tau_singlet, tau_triplet, singlet_fraction};
+            time_profile, tau_singlet, tau_triplet, singlet_fraction, wavelength_nm,
+            wavelength_fwhm_nm};
   Params prm{seed, pid_base, max_steps, eps, grad_material, surface_offset};
   const Material& gm = sc.mats[grad_material >= 0 ? grad_material : 0];
 #ifdef _OPENMP
@@ -708,6 +853,7 @@ int oracle_run(void* scene, int32_t kind, int32_t medium, int64_t n_photons, int
       rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z;
       rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z;
       rec.time = p.time; rec.path_len = p.path_len; rec.sum_inv_r = p.sum_inv_r; rec.sum_inv_t = p.sum_inv_t;
+      rec.wavelength = p.wavelength;
     }
     if ((p.flag & 0xff) == F_DETECT) {
       const int64_t cell = int64_t(p.event) * sc.n_channels + sc.channel[p.sensor];
@@ -745,6 +891,37 @@ void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
 }
 
 double oracle_u01(uint32_t x) { return u01(x); }
+
+// Emission wavelengths of photon ids pid0 .. pid0+n-1.
+void oracle_wavelength(uint64_t seed, uint64_t pid0, int64_t n, double mean, double fwhm,
+                       double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = emission_wavelength(seed, pid0 + uint64_t(i), mean, fwhm);
+}
+
+// Power reflectances |r_s|^2, |r_p|^2 of a model-1/2 surface for n incidence
+// cosines (from a medium of index n1, vacuum wavelength lambda).
+void oracle_surface_reflectance(int32_t model, double n1, double n_re, double n_im, double film_n,
+                                double film_d_nm, double lambda, int64_t n, const double* cos_i,
+                                double* out_rs, double* out_rp) {
+  for (int64_t i = 0; i < n; ++i) {
+    C rs, rp;
+    film_reflection(model, n1, cos_i[i], n_re, n_im, film_n, film_d_nm, lambda, rs, rp);
+    out_rs[i] = std::norm(rs);
+    out_rp[i] = std::norm(rp);
+  }
+}
+
+// Material properties at wavelengths lambda[0..n) (index, absorption and
+// Rayleigh lengths into out[3 i .. 3 i + 2]).
+void oracle_material_at(void* scene, int32_t m, int64_t n, const double* lambda, double* out) {
+  const Scene& sc = *static_cast<Scene*>(scene);
+  for (int64_t i = 0; i < n; ++i) {
+    const Material q = material_at(sc, m, lambda[i]);
+    out[3 * i] = q.n;
+    out[3 * i + 1] = q.abs_length;
+    out[3 * i + 2] = q.rayleigh_length;
+  }
+}
 
 // Scintillation emission times of photon ids pid0 .. pid0+n-1 and their state
 // (1 singlet, 0 triplet).

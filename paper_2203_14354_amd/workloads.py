@@ -56,6 +56,9 @@ class Material:
     n: float
     abs_length: float
     rayleigh_length: float
+    # optional dispersion table: rows (wavelength nm, n, L_abs, L_Rayleigh),
+    # wavelengths ascending, at most 8 rows
+    dispersion: Optional[np.ndarray] = None
 
 
 @dataclasses.dataclass
@@ -67,6 +70,14 @@ class Surface:
     p_transmit: float = 0.0
     grad_param: int = -1
     flags: int = 0
+    # reflectance model: 0 explicit partition (above), 1 complex index
+    # n_re + i n_im behind the surface, 2 a film (film_n, film_thickness_nm) on
+    # that substrate
+    model: int = 0
+    n_re: float = 0.0
+    n_im: float = 0.0
+    film_n: float = 0.0
+    film_thickness_nm: float = 0.0
 
 
 def split_reflectivity(r_total: float, spec_over_diff: float):
@@ -95,8 +106,29 @@ def materials_array(mats: Sequence[Material]) -> np.ndarray:
 def surfaces_array(surfs: Sequence[Surface]):
     p = np.array([[s.p_detect, s.p_absorb, s.r_diffuse, s.r_specular, s.p_transmit]
                   for s in surfs], dtype=np.float32).reshape(-1, 5)
-    tags = np.array([[s.grad_param, s.flags] for s in surfs], dtype=np.int32).reshape(-1, 2)
-    return p, tags
+    tags = np.array([[s.grad_param, s.flags, s.model] for s in surfs],
+                    dtype=np.int32).reshape(-1, 3)
+    optics = np.array([[s.n_re, s.n_im, s.film_n, s.film_thickness_nm] for s in surfs],
+                      dtype=np.float32).reshape(-1, 4)
+    return p, tags, optics
+
+
+SURF_MODEL_EXPLICIT, SURF_MODEL_COMPLEX, SURF_MODEL_THIN_FILM = 0, 1, 2
+# silicon at 175 nm (section "Alternative designs", optical table of the 4-pi
+# design): n = 0.81, k = 1.86
+SILICON_N, SILICON_K = 0.81, 1.86
+
+
+def complex_surface(n_re, n_im, flags=0) -> Surface:
+    """A surface whose reflectance follows from the complex index behind it."""
+    return Surface(model=SURF_MODEL_COMPLEX, n_re=float(n_re), n_im=float(n_im), flags=flags)
+
+
+def thin_film_surface(film_n, film_thickness_nm, n_re, n_im, flags=0) -> Surface:
+    """A dielectric film of index film_n and the given thickness on a
+    substrate of complex index n_re + i n_im."""
+    return Surface(model=SURF_MODEL_THIN_FILM, n_re=float(n_re), n_im=float(n_im),
+                   film_n=float(film_n), film_thickness_nm=float(film_thickness_nm), flags=flags)
 
 
 # ----------------------------------------------------------------------------
@@ -764,6 +796,8 @@ class Sources:
     tau_singlet_ns: float = 0.0
     tau_triplet_ns: float = 0.0
     singlet_fraction: float = 0.0
+    wavelength_nm: float = 174.8               # mean of the emission spectrum
+    wavelength_fwhm_nm: float = 0.0            # 0: every photon at the mean
 
     @property
     def n_sources(self) -> int:
@@ -832,6 +866,16 @@ def loss_components(mesh: Mesh, components=None):
             names.append(sname)
     lut = np.array([of_solid[i] for i in range(len(mesh.solid_names))], dtype=np.int32)
     return lut[mesh.solid], names
+
+
+# LXe scintillation spectrum (section "Optical properties"): Gaussian, mean
+# 174.8 nm, FWHM 10.2 nm
+SCINT_WAVELENGTH_NM, SCINT_FWHM_NM = 174.8, 10.2
+
+
+def with_spectrum(src: Sources, mean_nm=SCINT_WAVELENGTH_NM, fwhm_nm=SCINT_FWHM_NM) -> Sources:
+    """The same sources with wavelengths drawn from the Gaussian spectrum."""
+    return dataclasses.replace(src, wavelength_nm=float(mean_nm), wavelength_fwhm_nm=float(fwhm_nm))
 
 
 def uniform_points_in_cylinder(n, r_max, z_lo, z_hi, seed):
