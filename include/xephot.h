@@ -102,26 +102,64 @@ typedef struct xp_material {
   float rayleigh_length;   /* Rayleigh scattering length L_Rayleigh (m), > 0 */
 } xp_material;
 
-/* Set the material table (host array of n <= 8 entries, copied).
+/* Set the material table (host array of n <= 8 entries, copied).  Clears
+ * every dispersion table.
  * Errors: XP_ERR_INVALID_ARG (n out of range, a non-positive or NaN value). */
 int xp_set_materials(xp_context* ctx, const xp_material* m, int32_t n);
+
+/* Wavelength dependence of material `material` (section "Optical
+ * properties": the paper tabulates its values at the mean of the emission
+ * spectrum): n_points <= 8 samples at ascending wavelengths lambda_nm (host
+ * arrays, copied) of the index and of the absorption and Rayleigh lengths (m,
+ * INFINITY allowed).  At a photon's wavelength the index and the attenuation
+ * coefficients 1/L are interpolated linearly between the two neighbouring
+ * samples and held constant outside them; the material's table entry is then
+ * not used.  n_points = 0 removes the table.  Gradient tallies and the
+ * backward pass reject a gradient material that has a table.
+ * Errors: XP_ERR_STATE (material not set), XP_ERR_INVALID_ARG. */
+int xp_set_material_dispersion(xp_context* ctx, int32_t material, int32_t n_points,
+                               const float* lambda_nm, const float* index,
+                               const float* abs_length, const float* rayleigh_length);
 
 #define XP_SURF_DETECT_FRONT_ONLY 1 /* detect only photons arriving from the outer side;
                                        from the inner side the surface absorbs */
 
-/* An explicit surface: the probabilities partition [0, 1) in the order
- * detect | absorb | diffuse (Lambertian) | specular | transmit, independent of
- * the angle of incidence; any rounding remainder absorbs.  `grad_param` tags
- * the surface for the gradient tallies: 2 = reflectivity parameter (scales the
- * diffuse and specular parts together), 3 = transparency parameter, -1 none. */
+/* Surface models.
+ * EXPLICIT: the probabilities partition [0, 1) in the order
+ *   detect | absorb | diffuse (Lambertian) | specular | transmit, independent of
+ *   the angle of incidence; any rounding remainder absorbs.  `grad_param` tags
+ *   the surface for the gradient tallies: 2 = reflectivity parameter (scales
+ *   the diffuse and specular parts together), 3 = transparency parameter, -1
+ *   none.
+ * COMPLEX_INDEX: behind the surface lies a medium of complex index
+ *   n_re + i n_im (n_im >= 0: absorbing), e.g. the silicon of the 4-pi design's
+ *   optical table (0.81 + 1.86 i).  THIN_FILM: a dielectric film of index
+ *   film_n and thickness film_thickness_nm on such a medium (an Al/MgF2
+ *   coating).  For both, a photon arriving from a medium of index n1 is
+ *   reflected specularly with probability a_s^2 |r_s|^2 + a_p^2 |r_p|^2 (a_s,
+ *   a_p: components of its linear polarization along s and p; amplitude
+ *   coefficients in the Born and Wolf convention with q = sqrt(n^2 - n1^2
+ *   sin^2), principal branch, and the film phase 2 pi d q_film / lambda at the
+ *   photon's wavelength); the reflected photon stays linearly polarized, its s
+ *   and p components scaled by |r| with the sign of Re r.  A photon not
+ *   reflected is detected if the triangle is a sensor, else absorbed.  The
+ *   probability fields are ignored; grad_param must be -1. */
+enum { XP_SURF_EXPLICIT = 0, XP_SURF_COMPLEX_INDEX = 1, XP_SURF_THIN_FILM = 2 };
+
 typedef struct xp_surface {
   float p_detect, p_absorb, r_diffuse, r_specular, p_transmit;
   int32_t grad_param;
-  int32_t flags;           /* XP_SURF_* */
+  int32_t flags;           /* XP_SURF_DETECT_FRONT_ONLY */
+  int32_t model;           /* XP_SURF_EXPLICIT / COMPLEX_INDEX / THIN_FILM */
+  float n_re, n_im;        /* complex index behind the surface */
+  float film_n;            /* THIN_FILM: film index (> 0) */
+  float film_thickness_nm; /* THIN_FILM: film thickness (>= 0) */
 } xp_surface;
 
-/* Set the surface table (host array of n <= 16 entries, copied).  Each
- * entry's probabilities must be in [0, 1] and sum to 1 +- 1e-6.
+/* Set the surface table (host array of n <= 16 entries, copied).  An
+ * EXPLICIT entry's probabilities must be in [0, 1] and sum to 1 +- 1e-6; a
+ * COMPLEX_INDEX or THIN_FILM entry needs finite n_re > 0, n_im >= 0 (and
+ * film_n > 0, film_thickness_nm >= 0).
  * Errors: XP_ERR_INVALID_ARG. */
 int xp_set_surfaces(xp_context* ctx, const xp_surface* s, int32_t n);
 
@@ -198,6 +236,12 @@ typedef struct xp_sources {
   float tau_singlet_ns;       /* SCINTILLATION: decay constants (> 0) and the fraction */
   float tau_triplet_ns;       /*   of photons from the singlet state (in [0, 1]); the */
   float singlet_fraction;     /*   paper's optical table gives 3.5 ns, 24 ns, 0.66 (NR) */
+  float wavelength_nm;        /* mean of the Gaussian emission spectrum (174.8 in the
+                                 paper); >= 0, and > 0 when a THIN_FILM surface exists */
+  float wavelength_fwhm_nm;   /* its FWHM (10.2 in the paper); 0: every photon at the
+                                 mean.  Photon id pid draws (u0, u1) from Philox block
+                                 (step 0, sub 3): lambda = mean + sigma sqrt(-2 ln u0)
+                                 cos(2 pi u1), sigma = FWHM / (2 sqrt(2 ln 2)) */
 } xp_sources;
 
 /* Emission time of the photons (section "Optical properties": scintillation
@@ -248,7 +292,8 @@ typedef struct xp_photon_record {
   float pos[3];  float time;       /* final position (m), time of flight (ns) */
   float dir[3];  float path_len;   /* final direction; path length in grad_material */
   float pol[3];  float sum_inv_r;  /* final polarization; sum of 1/R over tagged reflections */
-  float sum_inv_t; float pad[3];   /* sum of 1/T over tagged transmissions */
+  float sum_inv_t; float wavelength; /* sum of 1/T over tagged transmissions; nm */
+  float pad[2];
 } xp_photon_record;
 
 /* Launch the transport of src->n_photons photons on `stream` (asynchronous).
@@ -368,6 +413,19 @@ int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float
 int xp_sample_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet_ns,
                             float tau_triplet_ns, float singlet_fraction, float* out_t,
                             int32_t* out_singlet, xp_stream stream);
+
+/* Emission wavelengths (nm) of photon ids pid0 .. pid0+n-1 (device float
+ * out[n]), as xp_propagate draws them. */
+int xp_sample_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean_nm, float fwhm_nm,
+                         float* out, xp_stream stream);
+
+/* Power reflectances |r_s|^2 and |r_p|^2 (device float out_rs[n], out_rp[n])
+ * of a COMPLEX_INDEX or THIN_FILM surface at n incidence cosines (device
+ * float cos_i[n]) for light from a medium of index n1 at wavelength lambda_nm,
+ * as the transport evaluates them. */
+int xp_surface_reflectance(int32_t model, float n1, float n_re, float n_im, float film_n,
+                           float film_thickness_nm, float lambda_nm, int64_t n,
+                           const float* cos_i, float* out_rs, float* out_rp, xp_stream stream);
 
 /* Host-only (no device needed): build the safety grid of a mesh (host arrays)
  * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,

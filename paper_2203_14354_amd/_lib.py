@@ -38,7 +38,9 @@ class Surface(ctypes.Structure):
     _fields_ = [("p_detect", ctypes.c_float), ("p_absorb", ctypes.c_float),
                 ("r_diffuse", ctypes.c_float), ("r_specular", ctypes.c_float),
                 ("p_transmit", ctypes.c_float), ("grad_param", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("model", ctypes.c_int32), ("n_re", ctypes.c_float),
+                ("n_im", ctypes.c_float), ("film_n", ctypes.c_float),
+                ("film_thickness_nm", ctypes.c_float)]
 
 
 class BvhOptions(ctypes.Structure):
@@ -63,7 +65,8 @@ class Sources(ctypes.Structure):
                 ("polarizations", ctypes.c_void_p), ("cyl_radius", ctypes.c_float),
                 ("cyl_zlo", ctypes.c_float), ("cyl_zhi", ctypes.c_float),
                 ("time_profile", ctypes.c_int32), ("tau_singlet_ns", ctypes.c_float),
-                ("tau_triplet_ns", ctypes.c_float), ("singlet_fraction", ctypes.c_float)]
+                ("tau_triplet_ns", ctypes.c_float), ("singlet_fraction", ctypes.c_float),
+                ("wavelength_nm", ctypes.c_float), ("wavelength_fwhm_nm", ctypes.c_float)]
 
 
 class ExtraTallies(ctypes.Structure):
@@ -91,15 +94,17 @@ RECORD_DTYPE = np.dtype([
     ("event", np.int32), ("medium", np.int32), ("n_scatter", np.int32), ("reserved", np.int32),
     ("pos", np.float32, 3), ("time", np.float32), ("dir", np.float32, 3),
     ("path_len", np.float32), ("pol", np.float32, 3), ("sum_inv_r", np.float32),
-    ("sum_inv_t", np.float32), ("pad", np.float32, 3)])
+    ("sum_inv_t", np.float32), ("wavelength", np.float32), ("pad", np.float32, 2)])
 assert RECORD_DTYPE.itemsize == 96
 
 # every symbol the header declares
 EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_mesh",
-           "xp_set_materials", "xp_set_surfaces", "xp_set_channel_map", "xp_build_bvh",
+           "xp_set_materials", "xp_set_material_dispersion", "xp_set_surfaces",
+           "xp_set_channel_map", "xp_build_bvh",
            "xp_bvh_stats", "xp_propagate", "xp_propagate_ex", "xp_set_loss_groups",
            "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
-           "xp_sample_emission_time", "xp_safety_grid_host", "xp_version"]
+           "xp_sample_emission_time", "xp_sample_wavelength", "xp_surface_reflectance",
+           "xp_safety_grid_host", "xp_version"]
 
 _lib = None
 
@@ -121,6 +126,7 @@ def load():
         "xp_last_error": (ctypes.c_char_p, [P]),
         "xp_load_mesh": (ctypes.c_int, [P, P, I64, P, I64, P, P, P, P]),
         "xp_set_materials": (ctypes.c_int, [P, P, I32]),
+        "xp_set_material_dispersion": (ctypes.c_int, [P, I32, I32, P, P, P, P]),
         "xp_set_surfaces": (ctypes.c_int, [P, P, I32]),
         "xp_set_channel_map": (ctypes.c_int, [P, P, I32, I32]),
         "xp_build_bvh": (ctypes.c_int, [P, P]),
@@ -134,6 +140,8 @@ def load():
         "xp_closest_hit": (ctypes.c_int, [P, I64, P, P, P, F, F, I32, P, P, P]),
         "xp_sample": (ctypes.c_int, [I32, U64, U64, I64, P, P, F, F, F, P, P, P]),
         "xp_sample_emission_time": (ctypes.c_int, [U64, U64, I64, F, F, F, P, P, P]),
+        "xp_sample_wavelength": (ctypes.c_int, [U64, U64, I64, F, F, P, P]),
+        "xp_surface_reflectance": (ctypes.c_int, [I32, F, F, F, F, F, F, I64, P, P, P, P]),
         "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
         "xp_version": (ctypes.c_char_p, []),
     }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -30,6 +31,7 @@ struct xp_context {
   int32_t max_mat = -1, max_surf = -1, max_sensor = -1;
   // tables
   std::vector<xp_material> mats;
+  std::vector<std::vector<std::array<float, 4>>> disp;  // per material: (lambda, n, L_abs, L_R)
   std::vector<xp_surface> surfs;
   std::vector<int32_t> channel;
   int32_t n_channels = 0;
@@ -161,6 +163,12 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     default:
       return fail(ctx, XP_ERR_INVALID_ARG, "unknown source kind");
   }
+  if (!(src->wavelength_nm >= 0.0f) || !std::isfinite(src->wavelength_nm) ||
+      !(src->wavelength_fwhm_nm >= 0.0f) || !std::isfinite(src->wavelength_fwhm_nm))
+    return fail(ctx, XP_ERR_INVALID_ARG, "wavelength and FWHM must be finite and >= 0");
+  for (const xp_surface& sf : ctx->surfs)
+    if (sf.model == XP_SURF_THIN_FILM && !(src->wavelength_nm > 0.0f))
+      return fail(ctx, XP_ERR_INVALID_ARG, "a thin-film surface needs a wavelength > 0");
   if (src->time_profile == XP_TIME_SCINTILLATION) {
     if (!finite_pos(src->tau_singlet_ns) || !finite_pos(src->tau_triplet_ns) ||
         !(src->singlet_fraction >= 0.0f && src->singlet_fraction <= 1.0f))
@@ -217,6 +225,8 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.cyl_r = src->cyl_radius;
   a.cyl_zlo = src->cyl_zlo;
   a.cyl_zhi = src->cyl_zhi;
+  a.wl_mean = src->wavelength_nm;
+  a.wl_sigma = float(double(src->wavelength_fwhm_nm) / (2.0 * std::sqrt(2.0 * std::log(2.0))));
   a.time_profile = src->time_profile;
   a.tau_singlet = src->tau_singlet_ns;
   a.tau_triplet = src->tau_triplet_ns;
@@ -232,7 +242,17 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.mats[i].n = ctx->mats[i].n;
     a.mats[i].abs_len = ctx->mats[i].abs_length;
     a.mats[i].ray_len = ctx->mats[i].rayleigh_length;
+    const auto& t = ctx->disp[i];
+    a.disp[i].n = int32_t(t.size());
+    for (size_t k = 0; k < t.size(); ++k) {
+      a.disp[i].lambda[k] = t[k][0];
+      a.disp[i].index[k] = t[k][1];
+      a.disp[i].inv_abs[k] = std::isinf(t[k][2]) ? 0.0f : float(1.0 / double(t[k][2]));
+      a.disp[i].inv_ray[k] = std::isinf(t[k][3]) ? 0.0f : float(1.0 / double(t[k][3]));
+    }
+    if (!t.empty()) a.dispersive |= 1 << i;
   }
+
   for (size_t i = 0; i < ctx->surfs.size(); ++i) {
     const xp_surface& s = ctx->surfs[i];
     // cumulative thresholds of the partition, accumulated in double and rounded once
@@ -249,6 +269,11 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.surfs[i].inv_r = rtot > 0 ? float(1.0 / rtot) : 0.0f;
     a.surfs[i].inv_t = s.p_transmit > 0 ? float(1.0 / double(s.p_transmit)) : 0.0f;
     a.surfs[i].flags_grad = (s.flags & 0xff) | ((s.grad_param + 1) << 8);
+    a.surfs[i].model = s.model;
+    a.surfs[i].n_re = s.n_re;
+    a.surfs[i].n_im = s.n_im;
+    a.surfs[i].film_n = s.film_n;
+    a.surfs[i].two_pi_d = float(2.0 * 3.14159265358979323846 * double(s.film_thickness_nm));
   }
   const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size);
   if (lds > ctx->max_lds)
@@ -402,6 +427,34 @@ int xp_set_materials(xp_context* ctx, const xp_material* m, int32_t n) {
   }
   try {
     ctx->mats.assign(m, m + n);
+    ctx->disp.assign(size_t(n), {});
+  } catch (...) {
+    return fail(ctx, XP_ERR_OOM, "host allocation failed");
+  }
+  return XP_OK;
+}
+
+int xp_set_material_dispersion(xp_context* ctx, int32_t material, int32_t n_points,
+                               const float* lambda_nm, const float* index,
+                               const float* abs_length, const float* rayleigh_length) {
+  if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
+  if (material < 0 || material >= int32_t(ctx->mats.size()))
+    return fail(ctx, XP_ERR_STATE, "material id not in the material table");
+  if (n_points < 0 || n_points > xp::kMaxDispersion)
+    return fail(ctx, XP_ERR_INVALID_ARG, "a dispersion table has 0..8 samples");
+  if (n_points > 0 && (!lambda_nm || !index || !abs_length || !rayleigh_length))
+    return fail(ctx, XP_ERR_INVALID_ARG, "null dispersion array");
+  for (int32_t i = 0; i < n_points; ++i) {
+    if (!finite_pos(lambda_nm[i]) || (i > 0 && !(lambda_nm[i] > lambda_nm[i - 1])))
+      return fail(ctx, XP_ERR_INVALID_ARG, "wavelengths must be finite, > 0 and ascending");
+    if (!finite_pos(index[i]) || !(abs_length[i] > 0.0f) || !(rayleigh_length[i] > 0.0f))
+      return fail(ctx, XP_ERR_INVALID_ARG, "index finite > 0, lengths > 0 (INFINITY allowed)");
+  }
+  try {
+    auto& t = ctx->disp[size_t(material)];
+    t.clear();
+    for (int32_t i = 0; i < n_points; ++i)
+      t.push_back({lambda_nm[i], index[i], abs_length[i], rayleigh_length[i]});
   } catch (...) {
     return fail(ctx, XP_ERR_OOM, "host allocation failed");
   }
@@ -413,6 +466,21 @@ int xp_set_surfaces(xp_context* ctx, const xp_surface* s, int32_t n) {
   if (!s || n <= 0 || n > xp::kMaxSurfaces)
     return fail(ctx, XP_ERR_INVALID_ARG, "need 1..16 surfaces");
   for (int32_t i = 0; i < n; ++i) {
+    if (s[i].flags & ~XP_SURF_DETECT_FRONT_ONLY)
+      return fail(ctx, XP_ERR_INVALID_ARG, "unknown surface flag");
+    if (s[i].model == XP_SURF_COMPLEX_INDEX || s[i].model == XP_SURF_THIN_FILM) {
+      if (!finite_pos(s[i].n_re) || !(s[i].n_im >= 0.0f) || !std::isfinite(s[i].n_im))
+        return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": complex index needs n_re > 0, n_im >= 0");
+      if (s[i].model == XP_SURF_THIN_FILM &&
+          (!finite_pos(s[i].film_n) || !(s[i].film_thickness_nm >= 0.0f) ||
+           !std::isfinite(s[i].film_thickness_nm)))
+        return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": film needs film_n > 0, thickness >= 0");
+      if (s[i].grad_param != -1)
+        return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": reflectance models take no gradient tag");
+      continue;
+    }
+    if (s[i].model != XP_SURF_EXPLICIT)
+      return fail(ctx, XP_ERR_INVALID_ARG, "unknown surface model");
     const float p[5] = {s[i].p_detect, s[i].p_absorb, s[i].r_diffuse, s[i].r_specular,
                         s[i].p_transmit};
     double sum = 0.0;
@@ -425,8 +493,6 @@ int xp_set_surfaces(xp_context* ctx, const xp_surface* s, int32_t n) {
       return fail(ctx, XP_ERR_INVALID_ARG, "surface " + std::to_string(i) + ": probabilities do not sum to 1");
     if (s[i].grad_param != -1 && s[i].grad_param != 2 && s[i].grad_param != 3)
       return fail(ctx, XP_ERR_INVALID_ARG, "grad_param must be -1, 2 or 3");
-    if (s[i].flags & ~XP_SURF_DETECT_FRONT_ONLY)
-      return fail(ctx, XP_ERR_INVALID_ARG, "unknown surface flag");
   }
   try {
     ctx->surfs.assign(s, s + n);
@@ -564,6 +630,8 @@ int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params*
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     int rc = prepare(ctx, src, rp, lc, a, cfg, grid);
     if (rc != XP_OK) return rc;
+    if (d_grad && rp->grad_material >= 0 && ((a.dispersive >> rp->grad_material) & 1))
+      return fail(ctx, XP_ERR_UNSUPPORTED, "gradient tallies need a gradient material without a dispersion table");
     a.hit_map = d_hit_map;
     a.grad = d_grad;
     a.records = d_records;
@@ -637,6 +705,39 @@ int xp_time_quantile(const int32_t* d_time_hist, int64_t n_events, int32_t n_tim
   return XP_OK;
 }
 
+int xp_sample_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean_nm, float fwhm_nm,
+                         float* out, xp_stream stream) {
+  if (n < 0 || (n > 0 && !out) || !(mean_nm >= 0.0f) || !std::isfinite(mean_nm) ||
+      !(fwhm_nm >= 0.0f) || !std::isfinite(fwhm_nm))
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad wavelength sampler arguments");
+  if (n >= (int64_t(1) << 37)) return fail(nullptr, XP_ERR_INVALID_ARG, "too many samples");
+  if (n == 0) return XP_OK;
+  const float sigma = float(double(fwhm_nm) / (2.0 * std::sqrt(2.0 * std::log(2.0))));
+  const hipError_t e = xp::launch_wavelength(seed, pid0, n, mean_nm, sigma, out,
+                                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(wavelength)");
+  return XP_OK;
+}
+
+int xp_surface_reflectance(int32_t model, float n1, float n_re, float n_im, float film_n,
+                           float film_thickness_nm, float lambda_nm, int64_t n,
+                           const float* cos_i, float* out_rs, float* out_rp, xp_stream stream) {
+  if ((model != XP_SURF_COMPLEX_INDEX && model != XP_SURF_THIN_FILM) || !finite_pos(n1) ||
+      !finite_pos(n_re) || !(n_im >= 0.0f) || !std::isfinite(n_im) ||
+      (model == XP_SURF_THIN_FILM && (!finite_pos(film_n) || !(film_thickness_nm >= 0.0f) ||
+                                      !finite_pos(lambda_nm))) ||
+      n < 0 || (n > 0 && (!cos_i || !out_rs || !out_rp)))
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad reflectance arguments");
+  if (n >= (int64_t(1) << 37)) return fail(nullptr, XP_ERR_INVALID_ARG, "too many samples");
+  if (n == 0) return XP_OK;
+  const float two_pi_d = float(2.0 * 3.14159265358979323846 * double(film_thickness_nm));
+  const hipError_t e = xp::launch_reflectance(model, n1, n_re, n_im, film_n, two_pi_d, lambda_nm,
+                                              n, cos_i, out_rs, out_rp,
+                                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(reflectance)");
+  return XP_OK;
+}
+
 int xp_sample_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet_ns,
                             float tau_triplet_ns, float singlet_fraction, float* out_t,
                             int32_t* out_singlet, xp_stream stream) {
@@ -666,6 +767,8 @@ int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     int rc = prepare(ctx, src, rp, lc, a, cfg, grid);
     if (rc != XP_OK) return rc;
+    if (rp->grad_material >= 0 && ((a.dispersive >> rp->grad_material) & 1))
+      return fail(ctx, XP_ERR_UNSUPPORTED, "the backward pass needs a gradient material without a dispersion table");
     a.grad_hits = d_grad_hits;
     a.grad_params = d_grad_params;
     return launch(ctx, a, xp::kBackward, false, false, false, cfg, grid,

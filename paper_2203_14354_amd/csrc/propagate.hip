@@ -15,6 +15,10 @@
 // item 3); explicit angle-independent surfaces (detect / absorb / diffuse /
 // specular / transmit); Fresnel reflection and refraction with total internal
 // reflection at dielectric boundaries (quartz, LXe, GXe); detection at sensors.
+// Optionally: emission times from the scintillation decay, wavelengths from
+// the Gaussian emission spectrum with interpolated material properties, and
+// surfaces whose reflectance follows from a complex index or a thin film
+// (section "Alternative designs").
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -114,6 +118,7 @@ __device__ __forceinline__ f3 random_polarization(f3 d, float u) {
 struct Photon {
   f3 pos, dir, pol;
   float time;
+  float wavelength;  // nm
   int32_t medium, last_tri, steps, flag, event, sensor;
   float path_len;   // in the gradient material
   int32_t n_sca;    // Rayleigh scatters in the gradient material
@@ -190,6 +195,122 @@ __device__ __forceinline__ bool fresnel(Photon& p, f3 nhat, float n1, float n2, 
   const f3 dt = normalize(eta * d + (eta * ci - ct) * nhat);
   p.pol = normalize((ts * as) * s + (tp * ap) * cross(s, dt));
   p.dir = dt;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// wavelength dependence: dispersion tables, complex-index and thin-film surfaces
+// ---------------------------------------------------------------------------
+
+// Material at wavelength lam: the index and the attenuation coefficients 1/L
+// interpolated linearly between the neighbouring samples of its table, held
+// constant outside (materials without a table: their table entry).
+__device__ __forceinline__ DevMaterial material_at(const LaunchArgs& a, int32_t m, float lam) {
+  DevMaterial r = a.mats[m];
+  if (a.dispersive != 0 && ((a.dispersive >> m) & 1)) {
+    const DevDispersion& t = a.disp[m];
+    float n, ia, ir;
+    if (lam <= t.lambda[0]) {
+      n = t.index[0]; ia = t.inv_abs[0]; ir = t.inv_ray[0];
+    } else if (lam >= t.lambda[t.n - 1]) {
+      n = t.index[t.n - 1]; ia = t.inv_abs[t.n - 1]; ir = t.inv_ray[t.n - 1];
+    } else {
+      int32_t i = 0;
+      while (t.lambda[i + 1] < lam) ++i;
+      const float w = (lam - t.lambda[i]) / (t.lambda[i + 1] - t.lambda[i]);
+      n = t.index[i] + w * (t.index[i + 1] - t.index[i]);
+      ia = t.inv_abs[i] + w * (t.inv_abs[i + 1] - t.inv_abs[i]);
+      ir = t.inv_ray[i] + w * (t.inv_ray[i + 1] - t.inv_ray[i]);
+    }
+    r.n = n;
+    r.abs_len = ia > 0.0f ? 1.0f / ia : kInfF;
+    r.ray_len = ir > 0.0f ? 1.0f / ir : kInfF;
+  }
+  return r;
+}
+
+// minimal complex arithmetic in FP32
+struct cf { float re, im; };
+__device__ __forceinline__ cf c_add(cf a, cf b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cf c_sub(cf a, cf b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cf c_mul(cf a, cf b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cf c_div(cf a, cf b) {
+  const float d = 1.0f / (b.re * b.re + b.im * b.im);
+  return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
+}
+// principal square root (Re >= 0, the sign of Im follows the argument's)
+__device__ __forceinline__ cf c_sqrt(cf z) {
+  const float r = hypotf(z.re, z.im);
+  if (r == 0.0f) return {0.0f, 0.0f};
+  if (z.re >= 0.0f) {
+    const float t = sqrtf(0.5f * (r + z.re));
+    return {t, z.im / (2.0f * t)};
+  }
+  const float t = sqrtf(0.5f * (r - z.re));
+  return {fabsf(z.im) / (2.0f * t), copysignf(t, z.im)};
+}
+__device__ __forceinline__ float c_norm(cf z) { return z.re * z.re + z.im * z.im; }
+
+// Amplitude reflection coefficients (s, p) from a medium of index n1 at
+// incidence cosine ci on a medium of complex index (model COMPLEX_INDEX) or on
+// a film over it (THIN_FILM, phase 2 pi d q_f / lam): with
+// q_j = sqrt(n_j^2 - n1^2 sin^2), r_s = (q_a - q_b) / (q_a + q_b) and
+// r_p = (n_b^2 q_a - n_a^2 q_b) / (n_b^2 q_a + n_a^2 q_b) per interface, and
+// r = (r_01 + r_12 E) / (1 + r_01 r_12 E), E = exp(2 i phase), for the film.
+__device__ __forceinline__ void film_reflection(int32_t model, float n1, float ci, float n_re,
+                                                float n_im, float nf, float two_pi_d, float lam,
+                                                cf& rs, cf& rp) {
+  const float s2 = n1 * n1 * (1.0f - ci * ci);
+  const cf q1{n1 * ci, 0.0f};
+  const cf e1{n1 * n1, 0.0f};
+  const cf e2{n_re * n_re - n_im * n_im, 2.0f * n_re * n_im};
+  const cf q2 = c_sqrt(cf{e2.re - s2, e2.im});
+  if (model == XP_SURF_COMPLEX_INDEX) {
+    rs = c_div(c_sub(q1, q2), c_add(q1, q2));
+    rp = c_div(c_sub(c_mul(e2, q1), c_mul(e1, q2)), c_add(c_mul(e2, q1), c_mul(e1, q2)));
+    return;
+  }
+  const cf ef{nf * nf, 0.0f};
+  const cf qf = c_sqrt(cf{ef.re - s2, 0.0f});
+  const cf r01s = c_div(c_sub(q1, qf), c_add(q1, qf));
+  const cf r12s = c_div(c_sub(qf, q2), c_add(qf, q2));
+  const cf r01p = c_div(c_sub(c_mul(ef, q1), c_mul(e1, qf)), c_add(c_mul(ef, q1), c_mul(e1, qf)));
+  const cf r12p = c_div(c_sub(c_mul(e2, qf), c_mul(ef, q2)), c_add(c_mul(e2, qf), c_mul(ef, q2)));
+  // E = exp(2 i k qf), k = 2 pi d / lam: modulus exp(-2 k Im qf), phase 2 k Re qf
+  const float k = two_pi_d / lam;
+  const float mag = expf(-2.0f * k * qf.im);
+  float sp, cp;
+  sincosf(2.0f * k * qf.re, &sp, &cp);
+  const cf E{mag * cp, mag * sp};
+  const cf one{1.0f, 0.0f};
+  rs = c_div(c_add(r01s, c_mul(r12s, E)), c_add(one, c_mul(c_mul(r01s, r12s), E)));
+  rp = c_div(c_add(r01p, c_mul(r12p, E)), c_add(one, c_mul(c_mul(r01p, r12p), E)));
+}
+
+// Reflection off a complex-index / thin-film surface with probability
+// a_s^2 |r_s|^2 + a_p^2 |r_p|^2; the reflected photon keeps a linear
+// polarization, its s and p parts scaled by |r| with the sign of Re r.
+// Returns true if reflected.
+__device__ __forceinline__ bool model_reflection(Photon& p, f3 nhat, float n1, const DevSurface& s,
+                                                 float u) {
+  const f3 d = p.dir, e = p.pol;
+  const float ci = -dot(d, nhat);
+  cf rs, rp;
+  film_reflection(s.model, n1, ci, s.n_re, s.n_im, s.film_n, s.two_pi_d, p.wavelength, rs, rp);
+  const f3 sv = cross(d, nhat);
+  const float sl = sqrtf(dot(sv, sv));
+  const f3 sd = (sl < 1e-6f) ? e : (1.0f / sl) * sv;
+  const float as = dot(e, sd);
+  const float ap = dot(e, cross(sd, d));
+  const float R = as * as * c_norm(rs) + ap * ap * c_norm(rp);
+  if (!(u < R)) return false;
+  const f3 dr = normalize(d + (2.0f * ci) * nhat);
+  const float ms = copysignf(sqrtf(c_norm(rs)), rs.re);
+  const float mp = copysignf(sqrtf(c_norm(rp)), rp.re);
+  p.pol = normalize((ms * as) * sd + (mp * ap) * cross(sd, dr));
+  p.dir = dr;
   return true;
 }
 
@@ -485,8 +606,18 @@ __device__ __forceinline__ float emission_time(uint32_t s0, uint32_t s1, uint64_
   return -(singlet ? tau_singlet : tau_triplet) * logf(r.u1);
 }
 
+// Wavelength from the Gaussian emission spectrum: Philox block (step 0,
+// sub 3), Box-Muller.
+__device__ __forceinline__ float emission_wavelength(uint32_t s0, uint32_t s1, uint64_t pid,
+                                                     float mean, float sigma) {
+  if (!(sigma > 0.0f)) return mean;
+  const R4 r = draw(s0, s1, pid, 0u, 3u);
+  return mean + sigma * sqrtf(-2.0f * logf(r.u0)) * cospif(2.0f * r.u1);
+}
+
 __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
   p.time = 0.0f;
+  p.wavelength = emission_wavelength(a.seed_lo, a.seed_hi, pid, a.wl_mean, a.wl_sigma);
   if (a.time_profile == XP_TIME_SCINTILLATION) {
     bool singlet;
     p.time = emission_time(a.seed_lo, a.seed_hi, pid, a.tau_singlet, a.tau_triplet,
@@ -535,7 +666,7 @@ struct StepDraw {
 // Start step s = steps + 1: draw the free paths in the current medium.
 __device__ __forceinline__ StepDraw begin_step(Photon& p, const LaunchArgs& a, uint64_t pid) {
   const int32_t step = ++p.steps;
-  const DevMaterial m = a.mats[p.medium];
+  const DevMaterial m = material_at(a, p.medium, p.wavelength);
   const R4 r = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 0u);
   StepDraw sd;
   sd.d_abs = isinf(m.abs_len) ? kInfF : -m.abs_len * logf(r.u0);
@@ -570,7 +701,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
     return true;
   }
   const int32_t step = p.steps;
-  const DevMaterial m = a.mats[p.medium];
+  const DevMaterial m = material_at(a, p.medium, p.wavelength);
   const float d_abs = sd.d_abs, d_sca = sd.d_sca;
   const float d_bulk = fminf(d_abs, d_sca);
   const bool in_grad = p.medium == a.grad_material;
@@ -622,7 +753,20 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
         return true;
       }
       const float u = sd.u2;
-      if (u < s.c_detect) {
+      if (s.model != XP_SURF_EXPLICIT) {
+        // reflectance from the complex index or the film; a photon that is not
+        // reflected enters the surface's material: detected on a sensor
+        if (!model_reflection(p, n_back, material_at(a, m_from, p.wavelength).n, s, u)) {
+          if (is_sensor) {
+            p.flag |= F_DETECT;
+            p.sensor = sensor;
+          } else {
+            p.flag |= F_SURFACE_ABSORB;
+          }
+          return true;
+        }
+        p.pos = p.pos + a.surface_offset * n_back;
+      } else if (u < s.c_detect) {
         if (is_sensor) {
           p.flag |= F_DETECT;
           p.sensor = sensor;
@@ -630,8 +774,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
           p.flag |= F_SURFACE_ABSORB;
         }
         return true;
-      }
-      if (u < s.c_absorb) {
+      } else if (u < s.c_absorb) {
         if (is_sensor) {
           p.flag |= F_SENSOR_ABSORB;
           p.sensor = sensor;
@@ -639,26 +782,28 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
           p.flag |= F_SURFACE_ABSORB;
         }
         return true;
-      }
-      bool through = false;
-      if (u < s.c_diffuse) {
-        lambertian(p, n_back, draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 1u));
-        if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
-      } else if (u < s.c_specular) {
-        specular(p, N);
-        if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
-      } else if (s.p_transmit > 0.0f) {
-        p.medium = m_to;
-        through = true;
-        if (kGradAcc && gpar == 3) p.sum_inv_t += s.inv_t;
       } else {
-        p.flag |= is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB;
-        if (is_sensor) p.sensor = sensor;
-        return true;
+        bool through = false;
+        if (u < s.c_diffuse) {
+          lambertian(p, n_back, draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 1u));
+          if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
+        } else if (u < s.c_specular) {
+          specular(p, N);
+          if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
+        } else if (s.p_transmit > 0.0f) {
+          p.medium = m_to;
+          through = true;
+          if (kGradAcc && gpar == 3) p.sum_inv_t += s.inv_t;
+        } else {
+          p.flag |= is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB;
+          if (is_sensor) p.sensor = sensor;
+          return true;
+        }
+        p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
       }
-      p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
     } else {
-      const float n1 = a.mats[m_from].n, n2 = a.mats[m_to].n;
+      const float n1 = material_at(a, m_from, p.wavelength).n;
+      const float n2 = material_at(a, m_to, p.wavelength).n;
       bool through = true;
       if (n1 != n2) through = fresnel(p, n_back, n1, n2, sd.u2);
       if (through) p.medium = m_to;
@@ -820,7 +965,8 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
             rec.path_len = p.path_len;
             rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z;
             rec.sum_inv_r = p.sum_inv_r;
-            rec.sum_inv_t = p.sum_inv_t; rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
+            rec.sum_inv_t = p.sum_inv_t; rec.wavelength = p.wavelength;
+            rec.pad[0] = rec.pad[1] = 0.0f;
           }
           if (kCount) {
             atomicAdd(&blk_stats[fl], 1ull);
@@ -986,6 +1132,26 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   out_t[i] = b.tri >= 0 ? b.t : kInfF;
 }
 
+// emission wavelengths with the transport's random-number schedule (test hook)
+__global__ void wavelength_kernel(uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n, float mean,
+                                  float sigma, float* out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = emission_wavelength(s0, s1, pid0 + uint64_t(i), mean, sigma);
+}
+
+// |r_s|^2, |r_p|^2 of a complex-index / thin-film surface (test hook)
+__global__ void reflectance_kernel(int32_t model, float n1, float n_re, float n_im, float film_n,
+                                   float two_pi_d, float lam, int64_t n, const float* cos_i,
+                                   float* out_rs, float* out_rp) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cf rs, rp;
+  film_reflection(model, n1, cos_i[i], n_re, n_im, film_n, two_pi_d, lam, rs, rp);
+  out_rs[i] = c_norm(rs);
+  out_rp[i] = c_norm(rp);
+}
+
 // emission times with the transport's random-number schedule (test hook)
 __global__ void emission_time_kernel(uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n,
                                      float tau_singlet, float tau_triplet, float singlet_fraction,
@@ -1114,6 +1280,25 @@ hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float t
   hipLaunchKernelGGL(emission_time_kernel, dim3(uint32_t(grid)), dim3(block), 0, s,
                      uint32_t(seed), uint32_t(seed >> 32), pid0, n, tau_singlet, tau_triplet,
                      singlet_fraction, out_t, out_singlet);
+  return hipGetLastError();
+}
+
+hipError_t launch_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean, float sigma,
+                             float* out, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(wavelength_kernel, dim3(uint32_t(grid)), dim3(block), 0, s, uint32_t(seed),
+                     uint32_t(seed >> 32), pid0, n, mean, sigma, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reflectance(int32_t model, float n1, float n_re, float n_im, float film_n,
+                              float two_pi_d, float lambda, int64_t n, const float* cos_i,
+                              float* out_rs, float* out_rp, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(reflectance_kernel, dim3(uint32_t(grid)), dim3(block), 0, s, model, n1, n_re,
+                     n_im, film_n, two_pi_d, lambda, n, cos_i, out_rs, out_rp);
   return hipGetLastError();
 }
 

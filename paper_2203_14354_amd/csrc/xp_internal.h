@@ -53,11 +53,23 @@ struct DevMaterial {
   float n, abs_len, ray_len, pad;
 };
 
-// Explicit surface as cumulative thresholds of one uniform draw.
+// Surface: an explicit partition as cumulative thresholds of one uniform
+// draw, or (model != 0) a complex-index / thin-film reflector.
 struct DevSurface {
   float c_detect, c_absorb, c_diffuse, c_specular;  // cumulative sums, rounded once
   float p_transmit, inv_r, inv_t;                    // 1/(R_diff+R_spec), 1/T
   int32_t flags_grad;                                // flags | (grad_param + 1) << 8
+  int32_t model;                                     // XP_SURF_*
+  float n_re, n_im, film_n, two_pi_d;                // 2 pi film thickness (nm)
+};
+
+constexpr int kMaxDispersion = 8;
+// Material dispersion table: samples at ascending wavelengths of the index
+// and of the attenuation coefficients 1/L_abs, 1/L_Rayleigh (0: no process).
+struct DevDispersion {
+  int32_t n;
+  float lambda[kMaxDispersion], index[kMaxDispersion];
+  float inv_abs[kMaxDispersion], inv_ray[kMaxDispersion];
 };
 
 enum Mode : int32_t { kForward = 0, kBackward = 1 };
@@ -92,6 +104,8 @@ struct LaunchArgs {
   float cyl_r, cyl_zlo, cyl_zhi;
   int32_t time_profile;    // XP_TIME_*
   float tau_singlet, tau_triplet, singlet_fraction;
+  float wl_mean, wl_sigma; // emission spectrum (sigma 0: one line)
+  int32_t dispersive;      // bit m: material m has a dispersion table
   // run parameters
   uint32_t seed_lo, seed_hi;
   uint64_t pid_base;
@@ -115,6 +129,7 @@ struct LaunchArgs {
   int32_t n_groups;
   DevMaterial mats[kMaxMaterials];
   DevSurface surfs[kMaxSurfaces];
+  DevDispersion disp[kMaxMaterials];
 };
 
 // Per-cell lower bound of the distance to the nearest triangle (see safety.cpp).
@@ -160,5 +175,10 @@ hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float t
                                 int32_t* out_singlet, hipStream_t s);
 hipError_t launch_time_quantile(const int32_t* hist, int64_t n_events, int32_t n_bins,
                                 float bin_ns, float q, float* out, hipStream_t s);
+hipError_t launch_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean, float sigma,
+                             float* out, hipStream_t s);
+hipError_t launch_reflectance(int32_t model, float n1, float n_re, float n_im, float film_n,
+                              float two_pi_d, float lambda, int64_t n, const float* cos_i,
+                              float* out_rs, float* out_rp, hipStream_t s);
 
 }  // namespace xp

@@ -64,7 +64,9 @@ class DeviceSources:
                        time_profile=int(getattr(s, "time_profile", 0)),
                        tau_singlet_ns=float(getattr(s, "tau_singlet_ns", 0.0)),
                        tau_triplet_ns=float(getattr(s, "tau_triplet_ns", 0.0)),
-                       singlet_fraction=float(getattr(s, "singlet_fraction", 0.0)))
+                       singlet_fraction=float(getattr(s, "singlet_fraction", 0.0)),
+                       wavelength_nm=float(getattr(s, "wavelength_nm", 0.0)),
+                       wavelength_fwhm_nm=float(getattr(s, "wavelength_fwhm_nm", 0.0)))
 
 
 class Detector:
@@ -108,11 +110,21 @@ class Detector:
         arr = (Material * len(mats))(*[Material(m.n, m.abs_length, m.rayleigh_length)
                                        for m in mats])
         check(self.lib.xp_set_materials(self.ctx, arr, len(mats)), self.ctx)
+        for i, m in enumerate(mats):
+            tab = getattr(m, "dispersion", None)
+            if tab is not None:
+                t = np.ascontiguousarray(np.asarray(tab, dtype=np.float32).reshape(-1, 4).T)
+                cols = [np.ascontiguousarray(c) for c in t]
+                check(self.lib.xp_set_material_dispersion(
+                    self.ctx, i, t.shape[1], *[_host_ptr(c) for c in cols]), self.ctx)
         self.materials = list(mats)
 
     def set_surfaces(self, surfs):
         arr = (Surface * len(surfs))(*[Surface(s.p_detect, s.p_absorb, s.r_diffuse, s.r_specular,
-                                               s.p_transmit, s.grad_param, s.flags)
+                                               s.p_transmit, s.grad_param, s.flags,
+                                               getattr(s, "model", 0), getattr(s, "n_re", 0.0),
+                                               getattr(s, "n_im", 0.0), getattr(s, "film_n", 0.0),
+                                               getattr(s, "film_thickness_nm", 0.0))
                                        for s in surfs])
         check(self.lib.xp_set_surfaces(self.ctx, arr, len(surfs)), self.ctx)
         self.surfaces = list(surfs)
@@ -275,6 +287,28 @@ def sample_emission_time(seed, pid0, n, tau_singlet_ns, tau_triplet_ns, singlet_
                                       float(tau_triplet_ns), float(singlet_fraction), _ptr(t),
                                       _ptr(st), ctypes.c_void_p(current_stream(dev))))
     return t, st
+
+
+def sample_wavelength(seed, pid0, n, mean_nm, fwhm_nm, device="cuda"):
+    """Device emission-wavelength sampler with the transport's schedule (test hook)."""
+    lib = load()
+    dev = torch.device(device)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    check(lib.xp_sample_wavelength(int(seed), int(pid0), int(n), float(mean_nm), float(fwhm_nm),
+                                   _ptr(out), ctypes.c_void_p(current_stream(dev))))
+    return out
+
+
+def surface_reflectance(model, n1, n_re, n_im, cos_i: torch.Tensor, film_n=0.0, film_d_nm=0.0,
+                        lam=174.8):
+    """|r_s|^2, |r_p|^2 of a complex-index / thin-film surface on the device (test hook)."""
+    lib = load()
+    c = cos_i.to(torch.float32).contiguous()
+    rs, rp = torch.empty_like(c), torch.empty_like(c)
+    check(lib.xp_surface_reflectance(int(model), float(n1), float(n_re), float(n_im), float(film_n),
+                                     float(film_d_nm), float(lam), c.numel(), _ptr(c), _ptr(rs),
+                                     _ptr(rp), ctypes.c_void_p(current_stream(c.device))))
+    return rs, rp
 
 
 def records_to_numpy(rec: torch.Tensor) -> np.ndarray:

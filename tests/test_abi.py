@@ -45,8 +45,8 @@ def test_header_functions_are_exported(lib):
 def test_struct_layouts_match_header():
     from paper_2203_14354_amd import _lib
     assert ctypes.sizeof(_lib.Material) == 12
-    assert ctypes.sizeof(_lib.Surface) == 28
-    assert ctypes.sizeof(_lib.Sources) == 104
+    assert ctypes.sizeof(_lib.Surface) == 48
+    assert ctypes.sizeof(_lib.Sources) == 112
     assert ctypes.sizeof(_lib.ExtraTallies) == 24
     assert ctypes.sizeof(_lib.RunParams) == 32
     assert ctypes.sizeof(_lib.LaunchCfg) == 24
@@ -78,6 +78,12 @@ def test_argument_validation_without_device(lib):
     assert lib.xp_time_quantile(None, 0, 10, 1.0, 0.9, None, None) == 0   # nothing to do
     assert lib.xp_sample_emission_time(0, 0, 10, 3.5, 24.0, 1.5, None, None, None) == -1
     assert lib.xp_sample_emission_time(0, 0, 0, 3.5, 24.0, 0.5, None, None, None) == 0
+    assert lib.xp_set_material_dispersion(None, 0, 0, None, None, None, None) == -1
+    assert lib.xp_sample_wavelength(0, 0, 10, 174.8, -1.0, None, None) == -1
+    assert lib.xp_surface_reflectance(0, 1.69, 0.81, 1.86, 0, 0, 174.8, 0, None, None, None,
+                                      None) == -1  # model 0 has no reflectance formula
+    assert lib.xp_surface_reflectance(1, 1.69, 0.81, 1.86, 0, 0, 174.8, 0, None, None, None,
+                                      None) == 0
 
 
 def _point_triangle_distance(p, a, b, c):
