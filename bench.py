@@ -155,6 +155,7 @@ def main():
         extras.update(lce_map_rate(torch, W, dev))
         extras.update(arrival_time_and_losses(torch, W, Detector, mesh, det, dev, args.photons))
         extras.update(design_variants(torch, W, Detector, dev))
+        extras.update(spectrum_cost(torch, W, det, mesh, dev))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -320,6 +321,7 @@ def design_variants(torch, W, Detector, dev, n=20_000_000):
                      ("4pi_pmt2_copper_fsr", dict(side_array="pmt2")),
                      ("4pi_pmt2_coated_fsr", dict(side_array="pmt2", fsr="coated")),
                      ("4pi_pmt2_no_fsr", dict(side_array="pmt2", fsr=None)),
+                     ("4pi_pmt2_copper_fsr_silicon_plates", dict(side_array="pmt2", plates="silicon")),
                      ("4pi_sipm_copper_fsr", dict(side_array="sipm"))):
         m = W.darwin(**kw)
         t0 = time.perf_counter()
@@ -343,6 +345,26 @@ def design_variants(torch, W, Detector, dev, n=20_000_000):
     return {"design_variants": {"workload": f"DARWIN-scale variants, {n} photons uniform in the "
                                             "active volume each, NR scintillation profile",
                                 "variants": out}}
+
+
+def spectrum_cost(torch, W, det, mesh, dev, n=20_000_000):
+    """DARWIN-scale transport with per-photon wavelengths from the Gaussian
+    spectrum (174.8 nm, FWHM 10.2 nm) against one line: the extra draw per
+    photon; without dispersion tables the LCE does not change."""
+    out = {}
+    for name, src in (("one_line", W.darwin_tpc(n_photons=n, mesh=mesh).sources),
+                      ("gaussian_spectrum", W.with_spectrum(W.darwin_tpc(n_photons=n, mesh=mesh).sources))):
+        ds = det.sources(src)
+        hm = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+        run = lambda: det.propagate(ds, seed=3, hit_map=hm)
+        run()
+        d, _ = timed_launches(run, 3, torch)
+        hm.zero_()
+        run()
+        out[name] = {"photons_per_s": n / statistics.median(d), "lce": int(hm.sum()) / n}
+    return {"spectrum": {"workload": f"darwin_tpc, {n} photons", **out,
+                         "spectrum_over_one_line_time": out["one_line"]["photons_per_s"]
+                         / out["gaussian_spectrum"]["photons_per_s"]}}
 
 
 def cpu_baseline(W, mesh, seed, sample):

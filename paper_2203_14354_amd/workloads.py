@@ -348,7 +348,7 @@ DARWIN_SRC_ZHI = -0.001
 def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float = DARWIN_SEG_MAX,
            electrodes: bool = True, coating: Optional[str] = None, single_phase: bool = False,
            bottom_array: bool = True, side_array: Optional[str] = None,
-           fsr: Optional[str] = "copper") -> Mesh:
+           fsr: Optional[str] = "copper", plates: str = "absorbing") -> Mesh:
     """DARWIN-shaped dual-phase TPC (about 4.8e5 triangles) and the paper's
     design variants (section "Alternative designs"):
       coating      "gate" or "all": electrodes covered with Al/MgF2 (90 %
@@ -362,11 +362,14 @@ def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float
                    plates behind field-shaping rings instead of the liquid
                    PTFE wall (the 4-pi design);
       fsr          field-shaping rings of the 4-pi design: "copper" (45 %,
-                   specular / diffuse 3.5), "coated" (Al/MgF2, 90 %, 17) or None.
+                   specular / diffuse 3.5), "coated" (Al/MgF2, 90 %, 17) or None;
+      plates       backing plates of the 4-pi design: "absorbing" (the paper's
+                   final choice) or "silicon" (reflectance from n = 0.81,
+                   k = 1.86, the other option the paper tried).
     Sensor ids: top array, then bottom array, then the side array."""
     mb = MeshBuilder()
     LX, GX, QZ = 0, 1, 2
-    S_PTFE_L, S_PTFE_G, S_SS, S_PC, S_CAP, S_COAT, S_CU, S_SIPM = 0, 1, 2, 3, 4, 5, 6, 7
+    S_PTFE_L, S_PTFE_G, S_SS, S_PC, S_CAP, S_COAT, S_CU, S_SIPM, S_SI = 0, 1, 2, 3, 4, 5, 6, 7, 8
     surfaces = [reflector(0.99, 0.05, grad_param=GRAD_REFLECTIVITY),
                 reflector(0.80, 0.05),
                 Surface(r_specular=0.20, r_diffuse=0.10, p_absorb=0.70),
@@ -374,7 +377,8 @@ def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float
                 Surface(p_absorb=1.0),
                 reflector(0.90, 17.0),
                 reflector(0.45, 3.5),
-                Surface(r_specular=0.25, p_detect=0.75, flags=SURF_DETECT_FRONT_ONLY)]
+                Surface(r_specular=0.25, p_detect=0.75, flags=SURF_DETECT_FRONT_ONLY),
+                complex_surface(SILICON_N, SILICON_K)]
     GAS = LX if single_phase else GX
     S_GAS_WALL = S_PTFE_L if single_phase else S_PTFE_G
     # side wall: 16 bands in the liquid (left out by the 4-pi design), one band in the gas
@@ -436,11 +440,13 @@ def darwin(n_wall: int = 256, sensor_pitch: float = DARWIN_PITCH, seg_max: float
                     S_COAT if coated else S_SS, tag)
     if side_array:
         sid = _side_array(mb, n_wall, rings[0], iface_ring, side_array, fsr, sid, LX, QZ,
-                          S_CAP, S_PC, S_SIPM, {"copper": S_CU, "coated": S_COAT}.get(fsr))
+                          S_CAP, S_PC, S_SIPM, {"copper": S_CU, "coated": S_COAT}.get(fsr),
+                          S_SI if plates == "silicon" else S_CAP)
     mats = [LXE, GXE, QUARTZ]
     name = "darwin" + "".join(f"+{k}" for k, on in (
         (f"coat-{coating}", coating), ("single-phase", single_phase),
-        ("no-bottom", not bottom_array), (f"4pi-{side_array}-fsr-{fsr}", side_array)) if on)
+        ("no-bottom", not bottom_array), (f"4pi-{side_array}-fsr-{fsr}", side_array),
+        ("si-plates", side_array and plates == "silicon")) if on)
     return mb.build(mats, surfaces, n_sensors=sid, name=name)
 
 
@@ -492,7 +498,7 @@ def _rects(centre, u, w, half_u, half_w):
 
 
 def _side_array(mb, n_wall, bottom_ring, top_ring, kind, fsr, sid, LX, QZ, S_ABS, S_PC, S_SIPM,
-                S_FSR):
+                S_FSR, S_PLATE):
     z_lo, z_hi = DARWIN_Z_BOTCAP, DARWIN_Z_IFACE
     z_mid = 0.5 * (z_lo + z_hi)
     r_in = DARWIN_R_WALL
@@ -531,7 +537,7 @@ def _side_array(mb, n_wall, bottom_ring, top_ring, kind, fsr, sid, LX, QZ, S_ABS
     zax = np.broadcast_to([0.0, 0.0, 1.0], nrm.shape)
     half_side = a_plate * math.tan(math.pi / SIDE_PLATES)
     pc = a_plate * nrm + np.array([0, 0, z_mid])
-    _quads(mb, _rects(pc, tan, zax, half_side, 0.5 * (z_hi - z_lo)), -nrm, LX, LX, S_ABS, -1,
+    _quads(mb, _rects(pc, tan, zax, half_side, 0.5 * (z_hi - z_lo)), -nrm, LX, LX, S_PLATE, -1,
            "backing_plate")
     # sensors on each plate, centred; u along the plate, w along z
     if kind == "pmt2":
