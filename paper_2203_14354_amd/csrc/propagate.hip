@@ -398,16 +398,25 @@ struct Counters {
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
-// from LDS, the rest from global memory.
+// from LDS, the rest from global memory.  The box planes are fetched in the
+// order the ray meets them (near before far on each axis, by the signs of its
+// direction), so the slab test needs no per-axis min / max: with a
+// non-negative reciprocal the lower plane's entry distance is the smaller one
+// (rounding is monotone), and the reciprocals are never zero.
 __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                           int32_t n_lds, int32_t node, float4 (&q)[7]) {
+                                           int32_t n_lds, int32_t node, int32_t sx, int32_t sy,
+                                           int32_t sz, float4 (&q)[7]) {
+  // q[0..5] = near x, far x, near y, far y, near z, far z (by the ray's signs)
+  const int32_t idx[6] = {sx, 1 - sx, 2 + sy, 3 - sy, 4 + sz, 5 - sz};
   if (node < n_lds) {
 #pragma unroll
-    for (int i = 0; i < 7; ++i) q[i] = lds_nodes[node * 8 + i];
+    for (int i = 0; i < 6; ++i) q[i] = lds_nodes[node * 8 + idx[i]];
+    q[6] = lds_nodes[node * 8 + 6];
   } else {
     const float4* g = reinterpret_cast<const float4*>(gnodes + node);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) q[i] = g[i];
+    for (int i = 0; i < 6; ++i) q[i] = g[idx[i]];
+    q[6] = g[6];
   }
 }
 
@@ -467,10 +476,13 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
                                            float tmax, LaneStack& st, int32_t& node,
                                            int32_t& leaf, Counters& cnt) {
   float4 q[7];
-  fetch_node(gnodes, lds_nodes, n_lds, node, q);
+  const int32_t sx = int32_t(uint32_t(__float_as_int(inv.x)) >> 31);
+  const int32_t sy = int32_t(uint32_t(__float_as_int(inv.y)) >> 31);
+  const int32_t sz = int32_t(uint32_t(__float_as_int(inv.z)) >> 31);
+  fetch_node(gnodes, lds_nodes, n_lds, node, sx, sy, sz, q);
   if (kCount) cnt.nodes++;
-  const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};
-  const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};
+  const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};  // near planes
+  const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};  // far planes
   const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
   const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
   const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
@@ -484,8 +496,8 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
     const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
     const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
     const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
-    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    const float tn = fmaxf(fmaxf(t0x, t0y), fmaxf(t0z, 0.0f));
+    const float tf = fminf(fminf(t1x, t1y), fminf(t1z, tmax));
     const bool hit = child[i] != kEmptyChild && tn <= tf * 1.0000005f;
     key[i] = hit ? tn : kInfF;
     ent[i] = child[i];
