@@ -30,8 +30,11 @@ HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 # bytes one node visit and one triangle test read: seven of the eight 16-byte
 # vectors of a 128-byte node (boxes and child entries), one 48-byte record
 NODE_BYTES, TRI_BYTES = 112, 48
+# sources whose change can change what the profiled launch does (kernel code,
+# BVH construction and its defaults, launch defaults, build flags)
 KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
                   "paper_2203_14354_amd/csrc/safety.cpp", "paper_2203_14354_amd/csrc/xp_internal.h",
+                  "paper_2203_14354_amd/csrc/api.cpp", "paper_2203_14354_amd/runtime.py",
                   "paper_2203_14354_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
 

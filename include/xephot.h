@@ -175,7 +175,9 @@ int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_
 /* ------------------------------------------------------------------------- */
 
 typedef struct xp_bvh_options {
-  int32_t max_leaf_size;   /* triangles per leaf, 1..8 (default 4) */
+  int32_t max_leaf_size;   /* triangles per leaf, 1..8 (default 1: a search micro-step
+                              tests one triangle and visits one node, and single-triangle
+                              leaves keep the triangle tests fewest) */
   int32_t sah_bins;        /* SAH bins per axis, 4..64 (default 32) */
   int32_t safety_cells;    /* cells of the safety grid along the mesh's longest extent,
                               0..512 (0 = no grid, also when opts is NULL).  A step whose free

@@ -528,7 +528,7 @@ int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
   if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
-  const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
+  const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
   const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
   const int scells = opts ? opts->safety_cells : 0;
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)

@@ -73,7 +73,7 @@ class Detector:
     """A mesh + optical tables + BVH resident on one GPU."""
 
     def __init__(self, mesh, device=0, channel_of_sensor=None, n_channels=None,
-                 max_leaf_size=4, sah_bins=32, safety_cells=0):
+                 max_leaf_size=1, sah_bins=32, safety_cells=0):
         self.lib = load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.mesh = mesh

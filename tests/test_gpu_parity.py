@@ -232,6 +232,20 @@ def test_stack_spill_to_global_does_not_change_results(rt):
     assert torch.equal(a, b)
 
 
+def test_bvh_leaf_size_does_not_change_results(rt):
+    """Single-triangle leaves (the default) and packed leaves of up to 4 or 8
+    triangles give the same closest hits: DARWIN hit maps bit for bit."""
+    mesh = W.darwin()
+    src = W.darwin_tpc(n_photons=400_000, mesh=mesh).sources
+    maps = []
+    for leaf in (1, 4, 8):
+        det = rt.Detector(mesh, device=0, max_leaf_size=leaf)
+        maps.append(det.propagate(src, seed=6)["hit_map"].clone())
+        torch.cuda.synchronize()
+        det.close()
+    assert torch.equal(maps[0], maps[1]) and torch.equal(maps[0], maps[2])
+
+
 @pytest.mark.parametrize("geom", ["darwin", "tpc1"])
 def test_safety_grid_does_not_change_results(rt, geom):
     """Skipping the search where the free path ends before any triangle gives
