@@ -532,7 +532,9 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   return true;
 }
 
-// BVH closest hit: t in (tmin, b.t], ties to the lower triangle index.
+// BVH closest hit: t in (tmin, b.t], ties to the lower triangle index, for
+// the closest-hit test hook (the transport kernel runs the same node visits
+// and triangle tests as micro-steps of its lane state machine).
 //
 // Two phases that the lanes of a wave run in step.  Node phase: each lane
 // without a postponed leaf visits inner nodes (popping its stack when it has
@@ -860,7 +862,8 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // Every lane is EMPTY (no photon), TRAVERSING (searching the closest hit of
 // its photon's current step) or WAITING (hit found, interaction pending).
 // Each loop iteration every traversing lane takes one micro-step of its BVH
-// search: a stack pop, then one leaf's triangle tests or one node visit.  When
+// search: a pop if it holds nothing, one triangle test if it holds a leaf, a
+// second pop if that emptied its hands, one node visit if it holds a node.  When
 // at least `wave_batch` lanes of the wave are not traversing, the wave runs one
 // combined phase for all of them: the interaction of the waiting lanes (and
 // the tallies of photons that end), the refill of empty lanes from the photon
