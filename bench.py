@@ -30,18 +30,16 @@ HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 # bytes one node visit and one triangle test read: seven of the eight 16-byte
 # vectors of a 128-byte node (boxes and child entries), one 48-byte record
 NODE_BYTES, TRI_BYTES = 112, 48
-# sources whose change can change what the profiled launch does (kernel code,
-# BVH construction and its defaults, launch defaults, build flags)
-KERNEL_SOURCES = ["paper_2203_14354_amd/csrc/propagate.hip", "paper_2203_14354_amd/csrc/bvh.cpp",
-                  "paper_2203_14354_amd/csrc/safety.cpp", "paper_2203_14354_amd/csrc/xp_internal.h",
-                  "paper_2203_14354_amd/csrc/api.cpp", "paper_2203_14354_amd/runtime.py",
-                  "paper_2203_14354_amd/build.py"]
+# what decides the profiled launch: the built library (kernel code, BVH
+# construction, launch defaults; the build is deterministic, and comments do
+# not change it) and the Python defaults that choose the BVH options
+PROFILED_FILES = ["paper_2203_14354_amd/libxephot.so", "paper_2203_14354_amd/runtime.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
 
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in PROFILED_FILES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -53,7 +51,7 @@ def measured_traffic(photons_per_launch: int):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
-    m_hash = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", text)
+    m_hash = re.search(r"library_sha256_16:\s*([0-9a-f]+)", text)
     m_n = re.search(r"photons_per_launch:\s*(\d+)", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not (m_hash and m_n and m_b):
@@ -184,7 +182,7 @@ def main():
                        "lane_steps_per_phase": n_steps / max(st[15], 1),
                        "geometry_errors": st[8], "escaped": st[5], "max_steps": st[6],
                        "nan_aborts": st[7]},
-        "kernel_sources_sha256_16": kernel_hash(),
+        "library_sha256_16": kernel_hash(),
     }
     line.update(extras)
     print(json.dumps(line), flush=True)
