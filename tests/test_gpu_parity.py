@@ -232,6 +232,36 @@ def test_stack_spill_to_global_does_not_change_results(rt):
     assert torch.equal(a, b)
 
 
+def test_darwin_full_size_sampled(rt):
+    """The benchmark's workload at its full size (1e8 photons, default launch
+    configuration): the hit map with per-photon records equals the plain
+    launch's; the oracle recomputes 2,000 photons sampled over the whole id
+    range one by one."""
+    from paper_2203_14354_amd._lib import RECORD_DTYPE
+    mesh = W.darwin()
+    det = rt.Detector(mesh, device=0)
+    n = 100_000_000
+    src = W.darwin_tpc(n_photons=n, mesh=mesh).sources
+    plain = det.propagate(src, seed=0)["hit_map"].clone()
+    out = det.propagate(src, seed=0, records=True)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, out["hit_map"])
+    idx = np.sort(np.random.default_rng(1).choice(n, 2_000, replace=False))
+    rec = out["records"][torch.from_numpy(idx).cuda()].cpu().numpy()
+    gpu = rec.view(RECORD_DTYPE).reshape(-1)
+    del out
+    torch.cuda.synchronize()
+    assert int(plain.sum()) == pytest.approx(0.3254 * n, rel=0.01)
+    sc = oracle.Scene(mesh, use_bvh=True)
+    ag = []
+    for k, i in enumerate(idx):
+        r = oracle.run(sc, src, seed=0, i_begin=int(i), i_end=int(i) + 1)["records"][0]
+        g = gpu[k]
+        ag.append(r["flag"] == g["flag"] and r["last_tri"] == g["last_tri"] and
+                  r["steps"] == g["steps"] and r["sensor"] == g["sensor"])
+    assert np.mean(ag) >= 0.998, np.mean(ag)
+
+
 def test_bvh_leaf_size_does_not_change_results(rt):
     """Single-triangle leaves (the default) and packed leaves of up to 4 or 8
     triangles give the same closest hits: DARWIN hit maps bit for bit."""
