@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gradient-overhead and batched measurements")
     ap.add_argument("--cpu-sample", type=int, default=5_000_000)
+    ap.add_argument("--cache-probe", action="store_true",
+                    help="only measure streaming-read bandwidth from buffers resident in the L2 "
+                         "caches (16 MB), the Infinity Cache (64-192 MB) and HBM (8 GB)")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES bytes (a known-traffic "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -105,6 +108,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.cache_probe:
+        print(json.dumps(cache_probe(torch, dev)), flush=True)
+        return
     if args.calibration_copy > 0:
         a = torch.ones(args.calibration_copy // 4, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -346,6 +352,33 @@ def design_variants(torch, W, Detector, dev, n=20_000_000):
     return {"design_variants": {"workload": f"DARWIN-scale variants, {n} photons uniform in the "
                                             "active volume each, NR scintillation profile",
                                 "variants": out}}
+
+
+def cache_probe(torch, dev):
+    """Streaming-read bandwidth of buffers that fit the eight 4 MB L2 caches
+    (16 MB: each XCD's workgroups touch one eighth), the 256 MB Infinity Cache
+    (64, 128, 192 MB) and only HBM (8 GB): one launch of 2048 x 256 threads
+    reads each buffer repeatedly (about 16 GB per launch); HIP events time 5
+    launches."""
+    import ctypes
+    from paper_2203_14354_amd import _lib
+    lib = _lib.load()
+    blocks = 2048
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    rates = {}
+    for name, mb in (("l2_16MB", 16), ("infinity_cache_64MB", 64), ("infinity_cache_128MB", 128),
+                     ("infinity_cache_192MB", 192), ("hbm_8GB", 8192)):
+        x = torch.ones(mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        n_vec = x.numel() // 4
+        passes = max(1, (16 << 30) // (mb << 20))
+        run = lambda: _lib.check(lib.xp_stream_read(ctypes.c_void_p(x.data_ptr()), n_vec, passes,
+                                                    blocks, ctypes.c_void_p(out.data_ptr()), stream))
+        run()
+        d, _ = timed_launches(run, 5, torch)
+        rates[name] = n_vec * 16 * passes / statistics.median(d) / 1e9
+        del x
+    return {"stream_read_GBps": rates}
 
 
 def spectrum_cost(torch, W, det, mesh, dev, n=20_000_000):

@@ -429,6 +429,14 @@ int xp_surface_reflectance(int32_t model, float n1, float n_re, float n_im, floa
                            float film_thickness_nm, float lambda_nm, int64_t n,
                            const float* cos_i, float* out_rs, float* out_rp, xp_stream stream);
 
+/* Bandwidth probe for the roofline (not part of the transport): `blocks`
+ * workgroups of 256 threads read the device buffer buf (n_vec 16-byte
+ * vectors) `passes` times with a grid stride and write one sum per thread to
+ * out (device float[blocks * 256]).  Buffers that fit the L2 caches or the
+ * Infinity Cache are then read from there on every pass after the first. */
+int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t blocks, float* out,
+                   xp_stream stream);
+
 /* Host-only (no device needed): build the safety grid of a mesh (host arrays)
  * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,
  * out_lo float[3] the grid origin, *out_cell the cell size; out_values

@@ -705,6 +705,16 @@ int xp_time_quantile(const int32_t* d_time_hist, int64_t n_events, int32_t n_tim
   return XP_OK;
 }
 
+int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t blocks, float* out,
+                   xp_stream stream) {
+  if (!buf || !out || n_vec <= 0 || passes <= 0 || blocks <= 0 || blocks > (1 << 20))
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad stream-read arguments");
+  const hipError_t e = xp::launch_stream_read(buf, n_vec, passes, blocks, out,
+                                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(stream_read)");
+  return XP_OK;
+}
+
 int xp_sample_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean_nm, float fwhm_nm,
                          float* out, xp_stream stream) {
   if (n < 0 || (n > 0 && !out) || !(mean_nm >= 0.0f) || !std::isfinite(mean_nm) ||

@@ -1147,6 +1147,20 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   out_t[i] = b.tri >= 0 ? b.t : kInfF;
 }
 
+// streaming read of a buffer, `passes` times with a grid stride (bandwidth probe)
+__global__ void __launch_bounds__(256) stream_read_kernel(const float4* __restrict__ buf, int64_t n,
+                                                          int32_t passes, float* out) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  float acc = 0.0f;
+  for (int32_t k = 0; k < passes; ++k)
+    for (int64_t i = gid; i < n; i += stride) {
+      const float4 v = buf[i];
+      acc += (v.x + v.y) + (v.z + v.w);
+    }
+  out[gid] = acc;
+}
+
 // emission wavelengths with the transport's random-number schedule (test hook)
 __global__ void wavelength_kernel(uint32_t s0, uint32_t s1, uint64_t pid0, int64_t n, float mean,
                                   float sigma, float* out) {
@@ -1295,6 +1309,13 @@ hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float t
   hipLaunchKernelGGL(emission_time_kernel, dim3(uint32_t(grid)), dim3(block), 0, s,
                      uint32_t(seed), uint32_t(seed >> 32), pid0, n, tau_singlet, tau_triplet,
                      singlet_fraction, out_t, out_singlet);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t blocks,
+                              float* out, hipStream_t s) {
+  hipLaunchKernelGGL(stream_read_kernel, dim3(uint32_t(blocks)), dim3(256), 0, s,
+                     static_cast<const float4*>(buf), n_vec, passes, out);
   return hipGetLastError();
 }
 
