@@ -83,7 +83,8 @@ class RunParams(ctypes.Structure):
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
-                ("stack_lds", ctypes.c_int32), ("wave_batch", ctypes.c_int32)]
+                ("stack_lds", ctypes.c_int32), ("wave_batch", ctypes.c_int32),
+                ("block_tally", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import os
 import shutil
+import concurrent.futures
 import subprocess
 import sys
 
@@ -23,7 +24,7 @@ LIB = os.path.join(HERE, "libxephot.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 HOST_SOURCES = ["api.cpp", "bvh.cpp", "safety.cpp"]
-DEVICE_SOURCES = ["propagate.hip"]
+DEVICE_SOURCES = ["propagate.hip", "propagate_tally.hip"]
 ARCH = "gfx950"
 
 
@@ -54,11 +55,11 @@ def build(verbose: bool = False) -> str:
     dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics", "-ffp-contract=on",
            "-fno-hip-fp32-correctly-rounded-divide-sqrt",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    objs = []
-    for s in HOST_SOURCES + DEVICE_SOURCES:
-        o = os.path.join(BUILD_DIR, s + ".o")
-        _run([hipcc, *common, *dev, "-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+    srcs = HOST_SOURCES + DEVICE_SOURCES
+    objs = [os.path.join(BUILD_DIR, s + ".o") for s in srcs]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(srcs)) as pool:
+        list(pool.map(lambda so: _run([hipcc, *common, *dev, "-c", os.path.join(CSRC, so[0]),
+                                       "-o", so[1]]), zip(srcs, objs)))
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -16,7 +16,7 @@
 #include "xp_internal.h"
 
 namespace xp {
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block);
+
 }
 
 struct xp_context {
@@ -115,7 +115,9 @@ int upload_channel_map(xp_context* ctx) {
   return XP_OK;
 }
 
-xp_launch_cfg default_cfg() { return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds, xp::kWaveBatch}; }
+xp_launch_cfg default_cfg() {
+  return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds, xp::kWaveBatch, 0};
+}
 
 // Validates (ctx, src, rp) for a launch and fills the kernel arguments.
 int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
@@ -185,6 +187,8 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (lc.wave_batch == 0) lc.wave_batch = xp::kWaveBatch;
   if (lc.wave_batch < 1 || lc.wave_batch > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "wave_batch must be in 1..64");
+  if (lc.block_tally < -1 || lc.block_tally > 1)
+    return fail(ctx, XP_ERR_INVALID_ARG, "block_tally must be -1, 0 or 1");
   if (lc.stack_lds < 4 || lc.stack_lds > 64 || (lc.stack_lds & (lc.stack_lds - 1)))
     return fail(ctx, XP_ERR_INVALID_ARG, "stack_lds must be a power of two in 4..64");
   if (lc.block_size != 64 && lc.block_size != 128 && lc.block_size != 256)
@@ -275,13 +279,13 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.surfs[i].film_n = s.film_n;
     a.surfs[i].two_pi_d = float(2.0 * 3.14159265358979323846 * double(s.film_thickness_nm));
   }
-  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size);
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size, 0, false);
   if (lds > ctx->max_lds)
     return fail(ctx, XP_ERR_UNSUPPORTED, "LDS request of " + std::to_string(lds) +
                                              " bytes exceeds the device limit; use fewer lds_levels "
                                              "or a smaller block");
   int per_cu = 0;
-  const hipError_t e = xp::max_blocks_per_cu(lc.block_size, lds, false, &per_cu);
+  const hipError_t e = xp::max_blocks_per_cu(lc.block_size, lds, false, false, &per_cu);
   if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
   if (per_cu <= 0) return fail(ctx, XP_ERR_UNSUPPORTED, "kernel does not fit on a CU");
   if (lc.blocks_per_cu <= 0 || lc.blocks_per_cu > per_cu) lc.blocks_per_cu = per_cu;
@@ -289,6 +293,30 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   if (int64_t(grid) * lc.block_size > ctx->stack_overflow_lanes)
     return fail(ctx, XP_ERR_UNSUPPORTED, "launch exceeds the traversal-stack overflow area");
   return XP_OK;
+}
+
+// Choose the per-workgroup LDS tallies of a forward launch (a.tally_cells):
+// they remove the atomic contention of small hit maps, which every photon of
+// a short-path detector hits; launches with records or counters, tallies too
+// large for LDS, or a lower occupancy keep the device-memory atomics.
+void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_launch_cfg& cfg,
+                        bool hits, bool grad, bool records, bool count, xp::LaunchArgs& a) {
+  a.tally_cells = 0;
+  if (cfg.block_tally < 0 || (!hits && !grad) || records || count) return;
+  const int64_t n_events =
+      (src->kind == XP_SRC_POINTS && src->per_source_events) ? src->n_sources : 1;
+  const int64_t cells = n_events * int64_t(ctx->n_channels);
+  if (cells <= 0 || cells > (cfg.block_tally > 0 ? int64_t(INT32_MAX) : xp::kAutoTallyCells))
+    return;
+  const size_t bytes = xp::tally_lds_bytes(int32_t(std::min<int64_t>(cells, 1 << 20)), grad);
+  if (bytes > xp::kMaxTallyBytes) return;
+  const size_t lds =
+      xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, cfg.block_size, int32_t(cells), grad);
+  int per_cu = 0;
+  if (lds <= ctx->max_lds &&
+      xp::max_blocks_per_cu(cfg.block_size, lds, false, true, &per_cu) == hipSuccess &&
+      per_cu >= cfg.blocks_per_cu)
+    a.tally_cells = int32_t(cells);
 }
 
 int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records, bool count,
@@ -653,6 +681,8 @@ int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params*
       a.tri_group = ctx->d_tri_group;
       a.n_groups = ctx->n_groups;
     }
+    choose_block_tally(ctx, src, cfg, d_hit_map != nullptr, d_grad != nullptr, d_records != nullptr,
+                       d_stats != nullptr, a);
     return launch(ctx, a, xp::kForward, d_grad != nullptr, d_records != nullptr, d_stats != nullptr,
                   cfg, grid, static_cast<hipStream_t>(stream));
   } catch (...) {
@@ -814,8 +844,18 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     for (int b : {64, 256})
       for (int l : {0, 3})
         for (int sl : {8, 16})
-          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb});
-    for (const xp_launch_cfg& cand : cands) {
+          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb, -1});
+    // then the fastest of these with the block tallies on
+    const size_t n_plain = cands.size();
+    for (size_t ci = 0; ci <= n_plain; ++ci) {
+      if (ci == n_plain) {
+        if (best_ms >= 1e30f) break;
+        xp_launch_cfg on = best;
+        on.block_tally = 1;
+        on.blocks_per_cu = 0;
+        cands.push_back(on);
+      }
+      const xp_launch_cfg cand = cands[ci];
       xp::LaunchArgs a;
       xp_launch_cfg cfg;
       int grid = 0;
@@ -826,6 +866,7 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
       }
       if (rc != XP_OK) break;
       a.hit_map = d_map;
+      choose_block_tally(ctx, &sample, cfg, true, false, false, false, a);
       float ms_best = 1e30f;
       for (int rep = 0; rep < 2 && rc == XP_OK; ++rep) {
         (void)hipEventRecord(t0, s);

@@ -1,1116 +1,11 @@
-// propagate.hip -- gfx950 kernels of the optical-photon transport.
-//
-// One lane carries one photon.  A workgroup stages the top levels of the
-// 4-wide BVH in LDS, then loops persistently: lanes whose photon has ended
-// are refilled from a per-wave pool of photon ids (one wave ballot, one
-// atomic per `chunk` photons), and every live lane advances its photon by one
-// step: free paths for absorption and Rayleigh scattering, closest hit along
-// the ray, then the bulk or surface interaction.  Photon i's random numbers
-// come from Philox-4x32-10 keyed by the seed with the photon id in the
-// counter, so results do not depend on which lane or wave runs the photon.
-//
-// The processes follow the paper's optical model (section "Optical
-// properties", table tab:optical): absorption and Rayleigh scattering with
-// exponential free paths; Rayleigh scattering with the dipole law (appendix
-// item 3); explicit angle-independent surfaces (detect / absorb / diffuse /
-// specular / transmit); Fresnel reflection and refraction with total internal
-// reflection at dielectric boundaries (quartz, LXe, GXe); detection at sensors.
-// Optionally: emission times from the scintillation decay, wavelengths from
-// the Gaussian emission spectrum with interpolated material properties, and
-// surfaces whose reflectance follows from a complex index or a thin film
-// (section "Alternative designs").
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdint>
-
-#include "xp_internal.h"
+// propagate.hip -- host launchers of the transport kernels, the kernel
+// variants without LDS tallies, and the small kernels behind the test hooks
+// (closest hit, emission sampling, reflectance, arrival-time quantiles,
+// streaming-read probe).  The transport itself is in transport.h.
+#include "transport.h"
 
 namespace xp {
 namespace {
-
-constexpr float kInfF = __builtin_huge_valf();
-constexpr float kCns = 0.299792458f;  // m/ns
-
-// ---------------------------------------------------------------------------
-// random numbers: Philox-4x32-10 (Salmon et al., SC'11)
-// ---------------------------------------------------------------------------
-struct R4 { float u0, u1, u2, u3; };
-
-__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    // one 32 x 32 -> 64-bit multiply-add instruction per product
-    const uint64_t p0 = uint64_t(c0) * 0xD2511F53ull;
-    const uint64_t p1 = uint64_t(c2) * 0xCD9E8D57ull;
-    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
-    c0 = n0;
-    c1 = uint32_t(p1);
-    c2 = n2;
-    c3 = uint32_t(p0);
-  }
-  return make_uint4(c0, c1, c2, c3);
-}
-
-// (2k + 1) / 2^24 from the top 23 bits: exact in FP32, strictly inside (0, 1)
-__device__ __forceinline__ float u01(uint32_t x) {
-  return (float(x >> 9) + 0.5f) * 1.1920928955078125e-7f;
-}
-
-__device__ __forceinline__ R4 draw(uint32_t seed_lo, uint32_t seed_hi, uint64_t pid, uint32_t step,
-                                   uint32_t sub) {
-  const uint4 r = philox(uint32_t(pid), uint32_t(pid >> 32), step, sub, seed_lo, seed_hi);
-  return R4{u01(r.x), u01(r.y), u01(r.z), u01(r.w)};
-}
-
-// ---------------------------------------------------------------------------
-// small vector algebra
-// ---------------------------------------------------------------------------
-struct f3 { float x, y, z; };
-__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ f3 cross(f3 a, f3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-__device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
-__device__ __forceinline__ bool finite3(f3 a) {
-  return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
-}
-__device__ __forceinline__ float comp(f3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
-
-// orthonormal basis of a unit vector (Duff et al., JCGT 2017) with the branch
-// switched at n_z = -1/2: for normals in the xy plane (detector walls) the sign
-// of n_z is rounding noise and must not select the basis
-__device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
-  const float s = n.z >= -0.5f ? 1.0f : -1.0f;
-  const float a = -1.0f / (s + n.z);
-  const float b = n.x * n.y * a;
-  b1 = {1.0f + s * n.x * n.x * a, s * b, -s * n.x};
-  b2 = {b, s + n.y * n.y * a, -n.y};
-}
-
-__device__ __forceinline__ f3 isotropic(float u0, float u1) {
-  const float c = 1.0f - 2.0f * u0;
-  const float s = sqrtf(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
-  float sp, cp;
-  sincospif(2.0f * u1, &sp, &cp);
-  return {s * cp, s * sp, c};
-}
-
-__device__ __forceinline__ f3 random_polarization(f3 d, float u) {
-  f3 b1, b2;
-  onb(d, b1, b2);
-  float sp, cp;
-  sincospif(2.0f * u, &sp, &cp);
-  return cp * b1 + sp * b2;
-}
-
-// ---------------------------------------------------------------------------
-// photon state
-// ---------------------------------------------------------------------------
-struct Photon {
-  f3 pos, dir, pol;
-  float time;
-  float wavelength;  // nm
-  int32_t medium, last_tri, steps, flag, event, sensor;
-  float path_len;   // in the gradient material
-  int32_t n_sca;    // Rayleigh scatters in the gradient material
-  float sum_inv_r, sum_inv_t;
-};
-
-enum : int32_t {
-  F_DETECT = 1, F_SENSOR_ABSORB = 2, F_SURFACE_ABSORB = 3, F_BULK_ABSORB = 4, F_ESCAPED = 5,
-  F_MAX_STEPS = 6, F_NAN_ABORT = 7, F_GEOM = 0x100
-};
-
-// dipole Rayleigh scattering: isotropic trial k', keep with probability
-// 1 - (e.k')^2; new polarization = e projected off k' (trial 64 kept if all fail)
-__device__ __forceinline__ void rayleigh(Photon& p, uint32_t s0, uint32_t s1, uint64_t pid,
-                                         uint32_t step) {
-  f3 k{0.f, 0.f, 1.f}, e{1.f, 0.f, 0.f};
-  for (uint32_t j = 0; j < 64; ++j) {
-    const R4 r = draw(s0, s1, pid, step, 2u + j);
-    k = isotropic(r.u0, r.u1);
-    const float ek = dot(p.pol, k);
-    e = p.pol - ek * k;
-    if (r.u2 < 1.0f - ek * ek) break;
-  }
-  p.dir = k;
-  p.pol = normalize(e);
-}
-
-// Lambertian reflection into the hemisphere of n_out, fresh polarization
-__device__ __forceinline__ void lambertian(Photon& p, f3 n_out, const R4& r) {
-  f3 b1, b2;
-  onb(n_out, b1, b2);
-  const float ct = sqrtf(r.u0);
-  const float st = sqrtf(fmaxf(0.0f, 1.0f - r.u0));
-  float sp, cp;
-  sincospif(2.0f * r.u1, &sp, &cp);
-  p.dir = normalize((st * cp) * b1 + (st * sp) * b2 + ct * n_out);
-  p.pol = random_polarization(p.dir, r.u2);
-}
-
-// mirror reflection about the plane of unit normal n (defined at normal incidence)
-__device__ __forceinline__ void specular(Photon& p, f3 n) {
-  p.dir = normalize(p.dir - (2.0f * dot(p.dir, n)) * n);
-  p.pol = normalize(p.pol - (2.0f * dot(p.pol, n)) * n);
-}
-
-// Fresnel at a real-index boundary; nhat points back into the incident medium.
-// Returns true if transmitted.
-__device__ __forceinline__ bool fresnel(Photon& p, f3 nhat, float n1, float n2, float u) {
-  const f3 d = p.dir, e = p.pol;
-  const float ci = -dot(d, nhat);
-  const float eta = n1 / n2;
-  const float st2 = eta * eta * (1.0f - ci * ci);
-  if (st2 >= 1.0f) {
-    specular(p, nhat);
-    return false;
-  }
-  const float ct = sqrtf(1.0f - st2);
-  const float rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
-  const float rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
-  const float ts = 2.0f * n1 * ci / (n1 * ci + n2 * ct);
-  const float tp = 2.0f * n1 * ci / (n2 * ci + n1 * ct);
-  const f3 sv = cross(d, nhat);
-  const float sl = sqrtf(dot(sv, sv));
-  const f3 s = (sl < 1e-6f) ? e : (1.0f / sl) * sv;
-  const float as = dot(e, s);
-  const float ap = dot(e, cross(s, d));
-  const float R = as * as * rs * rs + ap * ap * rp * rp;
-  if (u < R) {
-    const f3 dr = normalize(d + (2.0f * ci) * nhat);
-    p.pol = normalize((rs * as) * s + (rp * ap) * cross(s, dr));
-    p.dir = dr;
-    return false;
-  }
-  const f3 dt = normalize(eta * d + (eta * ci - ct) * nhat);
-  p.pol = normalize((ts * as) * s + (tp * ap) * cross(s, dt));
-  p.dir = dt;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
-// wavelength dependence: dispersion tables, complex-index and thin-film surfaces
-// ---------------------------------------------------------------------------
-
-// Material at wavelength lam: the index and the attenuation coefficients 1/L
-// interpolated linearly between the neighbouring samples of its table, held
-// constant outside (materials without a table: their table entry).
-__device__ __forceinline__ DevMaterial material_at(const LaunchArgs& a, int32_t m, float lam) {
-  DevMaterial r = a.mats[m];
-  if (a.dispersive != 0 && ((a.dispersive >> m) & 1)) {
-    const DevDispersion& t = a.disp[m];
-    float n, ia, ir;
-    if (lam <= t.lambda[0]) {
-      n = t.index[0]; ia = t.inv_abs[0]; ir = t.inv_ray[0];
-    } else if (lam >= t.lambda[t.n - 1]) {
-      n = t.index[t.n - 1]; ia = t.inv_abs[t.n - 1]; ir = t.inv_ray[t.n - 1];
-    } else {
-      int32_t i = 0;
-      while (t.lambda[i + 1] < lam) ++i;
-      const float w = (lam - t.lambda[i]) / (t.lambda[i + 1] - t.lambda[i]);
-      n = t.index[i] + w * (t.index[i + 1] - t.index[i]);
-      ia = t.inv_abs[i] + w * (t.inv_abs[i + 1] - t.inv_abs[i]);
-      ir = t.inv_ray[i] + w * (t.inv_ray[i + 1] - t.inv_ray[i]);
-    }
-    r.n = n;
-    r.abs_len = ia > 0.0f ? 1.0f / ia : kInfF;
-    r.ray_len = ir > 0.0f ? 1.0f / ir : kInfF;
-  }
-  return r;
-}
-
-// minimal complex arithmetic in FP32
-struct cf { float re, im; };
-__device__ __forceinline__ cf c_add(cf a, cf b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cf c_sub(cf a, cf b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cf c_mul(cf a, cf b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-__device__ __forceinline__ cf c_div(cf a, cf b) {
-  const float d = 1.0f / (b.re * b.re + b.im * b.im);
-  return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
-}
-// principal square root (Re >= 0, the sign of Im follows the argument's)
-__device__ __forceinline__ cf c_sqrt(cf z) {
-  const float r = hypotf(z.re, z.im);
-  if (r == 0.0f) return {0.0f, 0.0f};
-  if (z.re >= 0.0f) {
-    const float t = sqrtf(0.5f * (r + z.re));
-    return {t, z.im / (2.0f * t)};
-  }
-  const float t = sqrtf(0.5f * (r - z.re));
-  return {fabsf(z.im) / (2.0f * t), copysignf(t, z.im)};
-}
-__device__ __forceinline__ float c_norm(cf z) { return z.re * z.re + z.im * z.im; }
-
-// Amplitude reflection coefficients (s, p) from a medium of index n1 at
-// incidence cosine ci on a medium of complex index (model COMPLEX_INDEX) or on
-// a film over it (THIN_FILM, phase 2 pi d q_f / lam): with
-// q_j = sqrt(n_j^2 - n1^2 sin^2), r_s = (q_a - q_b) / (q_a + q_b) and
-// r_p = (n_b^2 q_a - n_a^2 q_b) / (n_b^2 q_a + n_a^2 q_b) per interface, and
-// r = (r_01 + r_12 E) / (1 + r_01 r_12 E), E = exp(2 i phase), for the film.
-__device__ __forceinline__ void film_reflection(int32_t model, float n1, float ci, float n_re,
-                                                float n_im, float nf, float two_pi_d, float lam,
-                                                cf& rs, cf& rp) {
-  const float s2 = n1 * n1 * (1.0f - ci * ci);
-  const cf q1{n1 * ci, 0.0f};
-  const cf e1{n1 * n1, 0.0f};
-  const cf e2{n_re * n_re - n_im * n_im, 2.0f * n_re * n_im};
-  const cf q2 = c_sqrt(cf{e2.re - s2, e2.im});
-  if (model == XP_SURF_COMPLEX_INDEX) {
-    rs = c_div(c_sub(q1, q2), c_add(q1, q2));
-    rp = c_div(c_sub(c_mul(e2, q1), c_mul(e1, q2)), c_add(c_mul(e2, q1), c_mul(e1, q2)));
-    return;
-  }
-  const cf ef{nf * nf, 0.0f};
-  const cf qf = c_sqrt(cf{ef.re - s2, 0.0f});
-  const cf r01s = c_div(c_sub(q1, qf), c_add(q1, qf));
-  const cf r12s = c_div(c_sub(qf, q2), c_add(qf, q2));
-  const cf r01p = c_div(c_sub(c_mul(ef, q1), c_mul(e1, qf)), c_add(c_mul(ef, q1), c_mul(e1, qf)));
-  const cf r12p = c_div(c_sub(c_mul(e2, qf), c_mul(ef, q2)), c_add(c_mul(e2, qf), c_mul(ef, q2)));
-  // E = exp(2 i k qf), k = 2 pi d / lam: modulus exp(-2 k Im qf), phase 2 k Re qf
-  const float k = two_pi_d / lam;
-  const float mag = expf(-2.0f * k * qf.im);
-  float sp, cp;
-  sincosf(2.0f * k * qf.re, &sp, &cp);
-  const cf E{mag * cp, mag * sp};
-  const cf one{1.0f, 0.0f};
-  rs = c_div(c_add(r01s, c_mul(r12s, E)), c_add(one, c_mul(c_mul(r01s, r12s), E)));
-  rp = c_div(c_add(r01p, c_mul(r12p, E)), c_add(one, c_mul(c_mul(r01p, r12p), E)));
-}
-
-// Reflection off a complex-index / thin-film surface with probability
-// a_s^2 |r_s|^2 + a_p^2 |r_p|^2; the reflected photon keeps a linear
-// polarization, its s and p parts scaled by |r| with the sign of Re r.
-// Returns true if reflected.
-__device__ __forceinline__ bool model_reflection(Photon& p, f3 nhat, float n1, const DevSurface& s,
-                                                 float u) {
-  const f3 d = p.dir, e = p.pol;
-  const float ci = -dot(d, nhat);
-  cf rs, rp;
-  film_reflection(s.model, n1, ci, s.n_re, s.n_im, s.film_n, s.two_pi_d, p.wavelength, rs, rp);
-  const f3 sv = cross(d, nhat);
-  const float sl = sqrtf(dot(sv, sv));
-  const f3 sd = (sl < 1e-6f) ? e : (1.0f / sl) * sv;
-  const float as = dot(e, sd);
-  const float ap = dot(e, cross(sd, d));
-  const float R = as * as * c_norm(rs) + ap * ap * c_norm(rp);
-  if (!(u < R)) return false;
-  const f3 dr = normalize(d + (2.0f * ci) * nhat);
-  const float ms = copysignf(sqrtf(c_norm(rs)), rs.re);
-  const float mp = copysignf(sqrtf(c_norm(rp)), rp.re);
-  p.pol = normalize((ms * as) * sd + (mp * ap) * cross(sd, dr));
-  p.dir = dr;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
-// ray / triangle (watertight, Woop, Benthin and Wald, JCGT 2013), FP32
-// ---------------------------------------------------------------------------
-// The ray in the frame of its dominant axis kz: origin rotated to
-// (kx, ky, kz) = (kz + 1, kz + 2, kz) mod 3, shear constants, and the first
-// record of the triangle copy rotated the same way.  The method swaps kx and ky
-// when d_kz < 0 to keep the winding; without the swap u, v, w, the determinant
-// and the distance numerator are all exactly negated (the products are not
-// contracted), which changes neither the inside test nor the distance.
-struct RayW {
-  f3 o;           // rotated origin
-  float sx, sy, sz;
-  int32_t toff;   // record offset of the rotated triangle copy
-};
-
-__device__ __forceinline__ RayW make_ray(f3 o, f3 d, int32_t n_tris) {
-  RayW r;
-  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
-  const int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-  const int kx = kz == 2 ? 0 : kz + 1;
-  const int ky = kx == 2 ? 0 : kx + 1;
-  r.o = f3{comp(o, kx), comp(o, ky), comp(o, kz)};
-  const float dz = comp(d, kz);
-  r.sx = comp(d, kx) / dz;
-  r.sy = comp(d, ky) / dz;
-  r.sz = 1.0f / dz;
-  r.toff = kx * n_tris;  // (kz + 1) mod 3 == kx
-  return r;
-}
-
-// hit distance or +inf; products are never contracted so that the edge
-// function of a shared edge is exactly negated between its two triangles
-__device__ __forceinline__ float intersect(const RayW& r, const float* va, const float* vb,
-                                           const float* vc) {
-  // vertices already rotated to (kx, ky, kz)
-  const f3 a{va[0] - r.o.x, va[1] - r.o.y, va[2] - r.o.z};
-  const f3 b{vb[0] - r.o.x, vb[1] - r.o.y, vb[2] - r.o.z};
-  const f3 c{vc[0] - r.o.x, vc[1] - r.o.y, vc[2] - r.o.z};
-  const float akz = a.z, bkz = b.z, ckz = c.z;
-  const float ax = fmaf(-r.sx, akz, a.x), ay = fmaf(-r.sy, akz, a.y);
-  const float bx = fmaf(-r.sx, bkz, b.x), by = fmaf(-r.sy, bkz, b.y);
-  const float cx = fmaf(-r.sx, ckz, c.x), cy = fmaf(-r.sy, ckz, c.y);
-  const float u = __fsub_rn(__fmul_rn(cx, by), __fmul_rn(cy, bx));
-  const float v = __fsub_rn(__fmul_rn(ax, cy), __fmul_rn(ay, cx));
-  const float w = __fsub_rn(__fmul_rn(bx, ay), __fmul_rn(by, ax));
-  if ((u < 0.0f || v < 0.0f || w < 0.0f) && (u > 0.0f || v > 0.0f || w > 0.0f)) return kInfF;
-  const float det = __fadd_rn(__fadd_rn(u, v), w);
-  if (det == 0.0f) return kInfF;
-  const float az = r.sz * akz, bz = r.sz * bkz, cz = r.sz * ckz;
-  const float t = __fadd_rn(__fadd_rn(__fmul_rn(u, az), __fmul_rn(v, bz)), __fmul_rn(w, cz));
-  return t * __builtin_amdgcn_rcpf(det);  // hardware reciprocal, 1 ulp
-}
-
-struct Best {
-  float t;
-  int32_t tri;   // mesh triangle index (-1: none)
-  int32_t rec;   // record index
-};
-
-__device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, int32_t k,
-                                              const RayW& r, float tmin, int32_t skip, Best& b) {
-  const TriRec& rec = tris[r.toff + k];  // the copy rotated for this ray
-  const float4 A = *reinterpret_cast<const float4*>(rec.a);
-  const float4 B = *reinterpret_cast<const float4*>(rec.b);
-  const float4 C = *reinterpret_cast<const float4*>(rec.c);
-  const int32_t id = __float_as_int(A.w);
-  if (id == skip) return;
-  const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
-  const float t = intersect(r, va, vb, vc);
-  if (!(t > tmin) || !(t <= b.t) || !(t < kInfF)) return;
-  if (t < b.t || b.tri < 0 || id < b.tri) {
-    b.t = t;
-    b.tri = id;
-    b.rec = k;
-  }
-}
-
-struct Counters {
-  uint32_t nodes, tris;
-  uint32_t slots, busy;  // search lane slots offered / used (SIMD utilization)
-  uint32_t skipped;      // searches skipped by the safety grid
-};
-
-// Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
-// from LDS, the rest from global memory.  The box planes are fetched in the
-// order the ray meets them (near before far on each axis, by the signs of its
-// direction), so the slab test needs no per-axis min / max: with a
-// non-negative reciprocal the lower plane's entry distance is the smaller one
-// (rounding is monotone), and the reciprocals are never zero.
-__device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                           int32_t n_lds, int32_t node, int32_t sx, int32_t sy,
-                                           int32_t sz, float4 (&q)[7]) {
-  // q[0..5] = near x, far x, near y, far y, near z, far z (by the ray's signs)
-  const int32_t idx[6] = {sx, 1 - sx, 2 + sy, 3 - sy, 4 + sz, 5 - sz};
-  if (node < n_lds) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) q[i] = lds_nodes[node * 8 + idx[i]];
-    q[6] = lds_nodes[node * 8 + 6];
-  } else {
-    const float4* g = reinterpret_cast<const float4*>(gnodes + node);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) q[i] = g[idx[i]];
-    q[6] = g[6];
-  }
-}
-
-// Per-lane traversal stack: the newest `lds_cap` entries (a power of two, at
-// least 4) in an LDS ring, older ones spilled to this lane's column of a
-// global overflow array.  A node visit first makes room for its (at most four)
-// pushes, then writes them without further tests.  `total` is the
-// host-computed worst case; a visit that would exceed it fails.
-struct LaneStack {
-  int32_t* lds;        // this lane's first LDS slot; slot k at lds[k * stride]
-  int32_t stride;
-  int32_t mask;        // lds_cap - 1
-  int32_t* glob;       // this lane's first overflow slot; slot k at glob[k * gstride]
-  int64_t gstride;
-  int32_t total;
-  int32_t sp, base;    // entries in use; entries held in the overflow array
-  // make room for four entries in the ring (the oldest move to the overflow array)
-  __device__ __forceinline__ void reserve4() {
-    while (sp - base > mask - 3) {
-      glob[int64_t(base) * gstride] = lds[__mul24(base & mask, stride)];
-      ++base;
-    }
-  }
-  // write entry j (< 4) above the top; valid after reserve4
-  __device__ __forceinline__ void put(int32_t j, int32_t e) {
-    lds[__mul24((sp + j) & mask, stride)] = e;
-  }
-  __device__ __forceinline__ int32_t pop() {
-    --sp;
-    if (sp < base) {
-      base = sp;
-      return glob[int64_t(sp) * gstride];
-    }
-    return lds[__mul24(sp & mask, stride)];
-  }
-};
-
-// compare-exchange of (key, value) pairs: ascending keys
-__device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t& vb) {
-  const bool sw = kb < ka;
-  const float k = sw ? kb : ka;
-  const int32_t v = sw ? vb : va;
-  kb = sw ? ka : kb;
-  vb = sw ? va : vb;
-  ka = k;
-  va = v;
-}
-
-// Visit one inner node: test its four child boxes, order the hits by entry
-// distance, follow the nearest inner child, postpone the nearest leaf (a leaf
-// the lane still holds is pushed) and push the rest far-first.  Stack
-// entries are node indices (>= 0) or complemented packed leaves
-// (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
-template <bool kCount>
-__device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
-                                           const float4* lds_nodes, int32_t n_lds, f3 inv, f3 oi,
-                                           float tmax, LaneStack& st, int32_t& node,
-                                           int32_t& leaf, Counters& cnt) {
-  float4 q[7];
-  const int32_t sx = int32_t(uint32_t(__float_as_int(inv.x)) >> 31);
-  const int32_t sy = int32_t(uint32_t(__float_as_int(inv.y)) >> 31);
-  const int32_t sz = int32_t(uint32_t(__float_as_int(inv.z)) >> 31);
-  fetch_node(gnodes, lds_nodes, n_lds, node, sx, sy, sz, q);
-  if (kCount) cnt.nodes++;
-  const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};  // near planes
-  const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};  // far planes
-  const float loy[4] = {q[2].x, q[2].y, q[2].z, q[2].w};
-  const float hiy[4] = {q[3].x, q[3].y, q[3].z, q[3].w};
-  const float loz[4] = {q[4].x, q[4].y, q[4].z, q[4].w};
-  const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
-  const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
-                            __float_as_int(q[6].z), __float_as_int(q[6].w)};
-  float key[4];
-  int32_t ent[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
-    const float t0y = fmaf(loy[i], inv.y, -oi.y), t1y = fmaf(hiy[i], inv.y, -oi.y);
-    const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
-    const float tn = fmaxf(fmaxf(t0x, t0y), fmaxf(t0z, 0.0f));
-    const float tf = fminf(fminf(t1x, t1y), fminf(t1z, tmax));
-    const bool hit = child[i] != kEmptyChild && tn <= tf * 1.0000005f;
-    key[i] = hit ? tn : kInfF;
-    ent[i] = child[i];
-  }
-  // ascending entry distance (a 5-comparator network); misses sort last
-  cswap(key[0], ent[0], key[1], ent[1]);
-  cswap(key[2], ent[2], key[3], ent[3]);
-  cswap(key[0], ent[0], key[2], ent[2]);
-  cswap(key[1], ent[1], key[3], ent[3]);
-  cswap(key[1], ent[1], key[2], ent[2]);
-  node = -1;
-  constexpr int32_t kNone = -1 - 0x7fffffff;
-  st.reserve4();
-  int32_t npush = 0;
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    const int32_t e = ent[i];
-    const bool hit = key[i] != kInfF;
-    int32_t spill = kNone;
-    if (hit && e < 0) {  // leaf: the nearer one keeps the slot
-      if (leaf >= 0) spill = ~leaf;
-      leaf = ~e;
-    } else if (hit) {    // inner node: the nearer one is followed
-      if (node >= 0) spill = node;
-      node = e;
-    }
-    st.put(npush, spill);  // a slot above the top: harmless when nothing spills
-    npush += spill != kNone ? 1 : 0;
-  }
-  if (st.sp + npush > st.total) return false;
-  st.sp += npush;
-  return true;
-}
-
-// BVH closest hit: t in (tmin, b.t], ties to the lower triangle index, for
-// the closest-hit test hook (the transport kernel runs the same node visits
-// and triangle tests as micro-steps of its lane state machine).
-//
-// Two phases that the lanes of a wave run in step.  Node phase: each lane
-// without a postponed leaf visits inner nodes (popping its stack when it has
-// none) until every lane of the wave holds a leaf or has run out of work.
-// Leaf phase: every lane holding a leaf tests its triangles.  Running the
-// phases separately keeps the wave's lanes on the same code (node tests or
-// triangle tests) instead of paying for both in every iteration.
-// Returns false only if the stack would overflow its host-computed bound.
-template <bool kCount>
-__device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                         int32_t n_lds, const TriRec* __restrict__ tris,
-                                         int32_t n_tris, LaneStack st, f3 o, f3 d, float tmin,
-                                         int32_t skip, Best& b, Counters& cnt) {
-  const RayW ray = make_ray(o, d, n_tris);
-  const float tiny = 1e-30f;
-  const f3 inv{1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
-               1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
-               1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z))};
-  const f3 oi{o.x * inv.x, o.y * inv.y, o.z * inv.z};
-  int32_t node = 0;   // inner node to visit next, or -1
-  int32_t leaf = -1;  // postponed leaf (packed), or -1
-  bool ok = true;
-  st.sp = 0;
-  st.base = 0;
-  while (true) {
-    // ---- node phase ----
-    while (true) {
-      const bool active = leaf < 0 && (node >= 0 || st.sp > 0);
-      if (kCount) {
-        cnt.slots++;
-        if (active) cnt.busy++;
-      }
-      if (active) {
-        if (node < 0) {
-          const int32_t e = st.pop();
-          if (e >= 0) node = e; else leaf = ~e;
-        }
-        if (node >= 0 && leaf < 0) {
-          if (!visit_node<kCount>(gnodes, lds_nodes, n_lds, inv, oi, b.t, st, node, leaf, cnt)) {
-            ok = false;
-            node = -1;
-            leaf = -1;
-            st.sp = 0;
-          }
-        }
-      }
-      if (__ballot(leaf < 0 && (node >= 0 || st.sp > 0)) == 0ull) break;
-    }
-    // ---- leaf phase ----
-    if (leaf >= 0) {
-      const int32_t first = leaf >> 3, n = (leaf & 7) + 1;
-      for (int32_t k = first; k < first + n; ++k) {
-        if (kCount) cnt.tris++;
-        test_triangle(tris, k, ray, tmin, skip, b);
-      }
-      leaf = -1;
-    }
-    if (__ballot(node >= 0 || st.sp > 0) == 0ull) break;
-  }
-  return ok;
-}
-
-// ---------------------------------------------------------------------------
-// sources
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t source_of(const LaunchArgs& a, int64_t i) {
-  if (a.offsets == nullptr) return i / a.count_per_source;
-  int64_t lo = 0, hi = a.n_sources;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a.offsets[mid] <= i) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Emission time from the two-component scintillation decay: Philox block
-// (step 0, sub 2), u0 picks the singlet state with its fraction, u1 the decay.
-__device__ __forceinline__ float emission_time(uint32_t s0, uint32_t s1, uint64_t pid,
-                                               float tau_singlet, float tau_triplet,
-                                               float singlet_fraction, bool& singlet) {
-  const R4 r = draw(s0, s1, pid, 0u, 2u);
-  singlet = r.u0 < singlet_fraction;
-  return -(singlet ? tau_singlet : tau_triplet) * logf(r.u1);
-}
-
-// Wavelength from the Gaussian emission spectrum: Philox block (step 0,
-// sub 3), Box-Muller.
-__device__ __forceinline__ float emission_wavelength(uint32_t s0, uint32_t s1, uint64_t pid,
-                                                     float mean, float sigma) {
-  if (!(sigma > 0.0f)) return mean;
-  const R4 r = draw(s0, s1, pid, 0u, 3u);
-  return mean + sigma * sqrtf(-2.0f * logf(r.u0)) * cospif(2.0f * r.u1);
-}
-
-__device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
-  p.time = 0.0f;
-  p.wavelength = emission_wavelength(a.seed_lo, a.seed_hi, pid, a.wl_mean, a.wl_sigma);
-  if (a.time_profile == XP_TIME_SCINTILLATION) {
-    bool singlet;
-    p.time = emission_time(a.seed_lo, a.seed_hi, pid, a.tau_singlet, a.tau_triplet,
-                           a.singlet_fraction, singlet);
-  }
-  p.medium = a.medium;
-  p.last_tri = -1;
-  p.steps = 0;
-  p.flag = 0;
-  p.event = 0;
-  p.sensor = -1;
-  p.path_len = 0.0f;
-  p.n_sca = 0;
-  p.sum_inv_r = 0.0f;
-  p.sum_inv_t = 0.0f;
-  if (a.src_kind == XP_SRC_EXPLICIT) {
-    p.pos = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
-    p.dir = normalize(f3{a.dirs[3 * i], a.dirs[3 * i + 1], a.dirs[3 * i + 2]});
-    const f3 e{a.pols[3 * i], a.pols[3 * i + 1], a.pols[3 * i + 2]};
-    p.pol = normalize(e - dot(e, p.dir) * p.dir);
-    return;
-  }
-  const R4 r = draw(a.seed_lo, a.seed_hi, pid, 0u, 0u);
-  p.dir = isotropic(r.u0, r.u1);
-  p.pol = random_polarization(p.dir, r.u2);
-  if (a.src_kind == XP_SRC_POINTS) {
-    const int64_t s = source_of(a, i);
-    p.pos = {a.positions[3 * s], a.positions[3 * s + 1], a.positions[3 * s + 2]};
-    p.event = a.per_source_events ? int32_t(s) : 0;
-  } else {
-    const R4 q = draw(a.seed_lo, a.seed_hi, pid, 0u, 1u);
-    const float rr = a.cyl_r * sqrtf(q.u0);
-    float sp, cp;
-    sincospif(2.0f * q.u1, &sp, &cp);
-    p.pos = {rr * cp, rr * sp, a.cyl_zlo + (a.cyl_zhi - a.cyl_zlo) * q.u2};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// one transport step, in two halves around the closest-hit search
-// ---------------------------------------------------------------------------
-struct StepDraw {
-  float d_abs, d_sca, u2;  // free paths to absorption and scattering; decision uniform
-};
-
-// Start step s = steps + 1: draw the free paths in the current medium.
-__device__ __forceinline__ StepDraw begin_step(Photon& p, const LaunchArgs& a, uint64_t pid) {
-  const int32_t step = ++p.steps;
-  const DevMaterial m = material_at(a, p.medium, p.wavelength);
-  const R4 r = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 0u);
-  StepDraw sd;
-  sd.d_abs = isinf(m.abs_len) ? kInfF : -m.abs_len * logf(r.u0);
-  sd.d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
-  sd.u2 = r.u2;
-  return sd;
-}
-
-// Lower bound of the distance from p to every triangle (0 outside the grid or
-// without one).
-__device__ __forceinline__ float safety_at(const LaunchArgs& a, f3 p) {
-  if (a.safety == nullptr) return 0.0f;
-  const float fx = (p.x - a.sg_lo[0]) * a.sg_inv_cell;
-  const float fy = (p.y - a.sg_lo[1]) * a.sg_inv_cell;
-  const float fz = (p.z - a.sg_lo[2]) * a.sg_inv_cell;
-  if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f)) return 0.0f;
-  const int32_t x = int32_t(fx), y = int32_t(fy), z = int32_t(fz);
-  if (x >= a.sg_n[0] || y >= a.sg_n[1] || z >= a.sg_n[2]) return 0.0f;
-  return a.safety[(int64_t(z) * a.sg_n[1] + y) * a.sg_n[0] + x];
-}
-
-// Finish the step given the closest hit b within min(d_abs, d_sca) (b.tri < 0:
-// none; b.tri == kTraversalFailed: the stack bound was exceeded).  Returns
-// true when the photon has ended.
-constexpr int32_t kTraversalFailed = -2;
-
-template <bool kGradAcc>
-__device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint64_t pid,
-                                            const StepDraw& sd, const Best& b) {
-  if (b.tri == kTraversalFailed) {
-    p.flag |= F_NAN_ABORT;  // prevented by the host's stack sizing
-    return true;
-  }
-  const int32_t step = p.steps;
-  const DevMaterial m = material_at(a, p.medium, p.wavelength);
-  const float d_abs = sd.d_abs, d_sca = sd.d_sca;
-  const float d_bulk = fminf(d_abs, d_sca);
-  const bool in_grad = p.medium == a.grad_material;
-  if (b.tri < 0) {
-    if (isinf(d_bulk)) {
-      p.flag |= F_ESCAPED;
-      return true;
-    }
-    p.pos = p.pos + d_bulk * p.dir;
-    p.time += d_bulk * m.n / kCns;
-    if (kGradAcc && in_grad) p.path_len += d_bulk;
-    if (d_abs <= d_sca) {
-      p.flag |= F_BULK_ABSORB;
-      return true;
-    }
-    if (kGradAcc && in_grad) p.n_sca += 1;
-    rayleigh(p, a.seed_lo, a.seed_hi, pid, uint32_t(step));
-    p.last_tri = -1;
-  } else {
-    const int32_t k = b.tri;
-    p.pos = p.pos + b.t * p.dir;
-    p.time += b.t * m.n / kCns;
-    if (kGradAcc && in_grad) p.path_len += b.t;
-    const float4 A = *reinterpret_cast<const float4*>(a.tris[b.rec].a);
-    const float4 B = *reinterpret_cast<const float4*>(a.tris[b.rec].b);
-    const float4 C = *reinterpret_cast<const float4*>(a.tris[b.rec].c);
-    const f3 v0{A.x, A.y, A.z};
-    const f3 N = normalize(cross(f3{B.x, B.y, B.z} - v0, f3{C.x, C.y, C.z} - v0));
-    const uint32_t packed = __float_as_uint(B.w);
-    const int32_t sensor = __float_as_int(C.w);
-    const int32_t mat_in = int32_t(packed & 0xffu), mat_out = int32_t((packed >> 8) & 0xffu);
-    const int32_t si = int32_t(packed >> 16) - 1;
-    const bool from_outer = dot(p.dir, N) < 0.0f;
-    const int32_t m_from = from_outer ? mat_out : mat_in;
-    const int32_t m_to = from_outer ? mat_in : mat_out;
-    if (m_from != p.medium) {
-      p.flag |= F_GEOM;
-      p.medium = m_from;
-    }
-    const f3 n_back = from_outer ? N : (-1.0f) * N;
-    p.last_tri = k;
-    if (si >= 0) {
-      const DevSurface s = a.surfs[si];
-      const int32_t sflags = s.flags_grad & 0xff;
-      const int32_t gpar = (s.flags_grad >> 8) - 1;
-      const bool is_sensor = sensor >= 0;
-      if ((sflags & XP_SURF_DETECT_FRONT_ONLY) && !from_outer) {
-        p.flag |= F_SURFACE_ABSORB;
-        return true;
-      }
-      const float u = sd.u2;
-      if (s.model != XP_SURF_EXPLICIT) {
-        // reflectance from the complex index or the film; a photon that is not
-        // reflected enters the surface's material: detected on a sensor
-        if (!model_reflection(p, n_back, material_at(a, m_from, p.wavelength).n, s, u)) {
-          if (is_sensor) {
-            p.flag |= F_DETECT;
-            p.sensor = sensor;
-          } else {
-            p.flag |= F_SURFACE_ABSORB;
-          }
-          return true;
-        }
-        p.pos = p.pos + a.surface_offset * n_back;
-      } else if (u < s.c_detect) {
-        if (is_sensor) {
-          p.flag |= F_DETECT;
-          p.sensor = sensor;
-        } else {
-          p.flag |= F_SURFACE_ABSORB;
-        }
-        return true;
-      } else if (u < s.c_absorb) {
-        if (is_sensor) {
-          p.flag |= F_SENSOR_ABSORB;
-          p.sensor = sensor;
-        } else {
-          p.flag |= F_SURFACE_ABSORB;
-        }
-        return true;
-      } else {
-        bool through = false;
-        if (u < s.c_diffuse) {
-          lambertian(p, n_back, draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 1u));
-          if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
-        } else if (u < s.c_specular) {
-          specular(p, N);
-          if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
-        } else if (s.p_transmit > 0.0f) {
-          p.medium = m_to;
-          through = true;
-          if (kGradAcc && gpar == 3) p.sum_inv_t += s.inv_t;
-        } else {
-          p.flag |= is_sensor ? F_SENSOR_ABSORB : F_SURFACE_ABSORB;
-          if (is_sensor) p.sensor = sensor;
-          return true;
-        }
-        p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
-      }
-    } else {
-      const float n1 = material_at(a, m_from, p.wavelength).n;
-      const float n2 = material_at(a, m_to, p.wavelength).n;
-      bool through = true;
-      if (n1 != n2) through = fresnel(p, n_back, n1, n2, sd.u2);
-      if (through) p.medium = m_to;
-      p.pos = p.pos + (through ? -a.surface_offset : a.surface_offset) * n_back;
-    }
-  }
-  if (!finite3(p.pos) || !finite3(p.dir) || !finite3(p.pol)) {
-    p.flag |= F_NAN_ABORT;
-    return true;
-  }
-  if (step >= a.max_steps) {
-    p.flag |= F_MAX_STEPS;
-    return true;
-  }
-  return false;
-}
-
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-}
-
-__device__ __forceinline__ uint64_t bcast64(uint64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(x));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(x >> 32));
-  return (uint64_t(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// the persistent transport kernel
-//   kMode: kForward (hit map, optional gradient tallies) or kBackward (replay)
-//
-// Every lane is EMPTY (no photon), TRAVERSING (searching the closest hit of
-// its photon's current step) or WAITING (hit found, interaction pending).
-// Each loop iteration every traversing lane takes one micro-step of its BVH
-// search: a pop if it holds nothing, one triangle test if it holds a leaf, a
-// second pop if that emptied its hands, one node visit if it holds a node.  When
-// at least `wave_batch` lanes of the wave are not traversing, the wave runs one
-// combined phase for all of them: the interaction of the waiting lanes (and
-// the tallies of photons that end), the refill of empty lanes from the photon
-// pool, and the start of the next step (free paths, ray set-up).  Lanes thus
-// never wait for the slowest search of the wave, and the long, branchy
-// interaction code runs once for many lanes instead of once per step.
-// ---------------------------------------------------------------------------
-enum : int32_t { kEmpty = 0, kTraversing = 1, kWaiting = 2 };
-
-// Five waves per SIMD (at most 96 VGPRs): the lane state of the search and the
-// photon fits without spilling; six or more waves force spills that cost more
-// than the extra latency hiding gains.
-template <int kMode, bool kGrad, bool kRecords, bool kCount>
-__global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
-  extern __shared__ float4 lds[];
-  constexpr bool kGradAcc = kGrad || kMode == kBackward;
-  float4* lds_nodes = lds;
-  int32_t* stack_base = reinterpret_cast<int32_t*>(lds + a.n_lds_nodes * 8);
-  unsigned long long* blk_stats =
-      reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
-  const float4* gn = reinterpret_cast<const float4*>(a.nodes);
-  for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
-  if (kCount)
-    for (int32_t i = threadIdx.x; i < kStatsWords; i += blockDim.x) blk_stats[i] = 0ull;
-  __syncthreads();
-  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  LaneStack stack{stack_base + threadIdx.x, int32_t(blockDim.x), a.stack_lds - 1,
-                  a.stack_overflow + gtid, int64_t(gridDim.x) * blockDim.x, a.stack_total, 0, 0};
-  const uint32_t lane = lane_rank(~0ull);
-  const uint32_t batch_trigger = 64u - uint32_t(a.wave_batch);  // run the phase at <= this
-
-  Photon p;
-  int32_t state = kEmpty;
-  int64_t idx = 0;
-  uint64_t pid = 0;
-  uint64_t pool_next = 0, pool_end = 0;
-  bool exhausted = false;
-  Counters cnt{0u, 0u, 0u, 0u, 0u};
-  uint32_t n_steps = 0;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // search state of the current step
-  StepDraw sd{0.f, 0.f, 0.f};
-  Best b{0.f, -1, -1};
-  RayW ray;
-  f3 inv{0.f, 0.f, 0.f}, oi{0.f, 0.f, 0.f};
-  int32_t node = -1, leaf = -1;
-
-  unsigned long long cyc_phase = 0, cyc_search = 0, n_phases = 0;
-  while (true) {
-    const uint32_t n_trav = uint32_t(__popcll(__ballot(state == kTraversing)));
-    unsigned long long t_mark = 0;
-    if (kCount) t_mark = clock64();
-    if (n_trav <= batch_trigger) {
-      if (kCount) n_phases++;
-      // ---- interaction of the waiting lanes ----
-      bool start = false;  // lanes that begin a new step in this phase
-      if (state == kWaiting) {
-        state = kTraversing;  // a new step follows unless the photon ends
-        start = true;
-        if (finish_step<kGradAcc>(p, a, pid, sd, b)) {
-          start = false;
-          state = kEmpty;
-          const int32_t fl = p.flag & 0xff;
-          if (fl == F_DETECT) {
-            const int64_t cell = int64_t(p.event) * a.n_channels + a.channel_of_sensor[p.sensor];
-            // score-function weights of the detected path, evaluated in FP64 (the
-            // Rayleigh-length score is a difference of two large terms)
-            double sc[4] = {0.0, 0.0, 0.0, 0.0};
-            if (kGradAcc) {
-              if (a.grad_material >= 0) {
-                const DevMaterial gm = a.mats[a.grad_material];
-                const double L = p.path_len, la = gm.abs_len, lr = gm.ray_len;
-                const double s0 = L / (la * la);
-                const double s1 = L / (lr * lr) - double(p.n_sca) / lr;
-                sc[0] = isfinite(s0) ? s0 : 0.0;
-                sc[1] = isfinite(s1) ? s1 : 0.0;
-              }
-              sc[2] = p.sum_inv_r;
-              sc[3] = p.sum_inv_t;
-            }
-            if (kMode == kForward) {
-              if (a.hit_map) atomicAdd(a.hit_map + cell, 1);
-              if (a.time_hist) {
-                // arrival time bin; the last bin is open-ended (also NaN lands there)
-                const float f = p.time * a.time_inv_bin;
-                const int32_t bin = f < float(a.n_time_bins - 1) ? int32_t(fmaxf(f, 0.0f))
-                                                                 : a.n_time_bins - 1;
-                atomicAdd(a.time_hist + int64_t(p.event) * a.n_time_bins + bin, 1);
-              }
-              if (kGrad && a.grad) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
-              }
-            } else {
-              const double w = double(a.grad_hits[cell]);
-#pragma unroll
-              for (int q = 0; q < 4; ++q) acc[q] += w * sc[q];
-            }
-          }
-          if (kMode == kForward && a.loss) {
-            // where the photon ended: the group of its last triangle for the
-            // surface terminals, else the material it was in
-            const bool on_surface = fl >= F_DETECT && fl <= F_SURFACE_ABSORB && p.last_tri >= 0;
-            const int64_t row = on_surface ? int64_t(a.tri_group[p.last_tri])
-                                           : int64_t(a.n_groups) + p.medium;
-            atomicAdd(a.loss + row * 8 + fl, 1ull);
-          }
-          if (kRecords) {
-            xp_photon_record& rec = a.records[idx];
-            rec.flag = p.flag; rec.last_tri = p.last_tri; rec.sensor = p.sensor; rec.steps = p.steps;
-            rec.event = p.event; rec.medium = p.medium; rec.n_scatter = p.n_sca; rec.reserved = 0;
-            rec.pos[0] = p.pos.x; rec.pos[1] = p.pos.y; rec.pos[2] = p.pos.z; rec.time = p.time;
-            rec.dir[0] = p.dir.x; rec.dir[1] = p.dir.y; rec.dir[2] = p.dir.z;
-            rec.path_len = p.path_len;
-            rec.pol[0] = p.pol.x; rec.pol[1] = p.pol.y; rec.pol[2] = p.pol.z;
-            rec.sum_inv_r = p.sum_inv_r;
-            rec.sum_inv_t = p.sum_inv_t; rec.wavelength = p.wavelength;
-            rec.pad[0] = rec.pad[1] = 0.0f;
-          }
-          if (kCount) {
-            atomicAdd(&blk_stats[fl], 1ull);
-            if (p.flag & F_GEOM) atomicAdd(&blk_stats[8], 1ull);
-          }
-        }
-      }
-      // ---- refill empty lanes from the photon pool (wave-uniform control flow) ----
-      uint64_t dead = __ballot(state == kEmpty);
-      while (dead != 0ull && !exhausted) {
-        if (pool_next >= pool_end) {
-          uint64_t base = 0;
-          if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
-          base = bcast64(base);
-          if (base >= uint64_t(a.n_photons)) {
-            exhausted = true;
-            break;
-          }
-          pool_next = base;
-          pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
-        }
-        const uint64_t avail = pool_end - pool_next;
-        const uint32_t rank = lane_rank(dead);
-        if (state == kEmpty && rank < avail) {
-          idx = int64_t(pool_next + rank);
-          pid = a.pid_base + uint64_t(idx);
-          state = kTraversing;
-          start = true;
-          emit(p, a, idx, pid);
-        }
-        const uint64_t ndead = uint64_t(__popcll(dead));
-        pool_next += ndead < avail ? ndead : avail;
-        dead = __ballot(state == kEmpty);
-      }
-      if (__ballot(state != kEmpty) == 0ull) break;  // pool exhausted and every lane idle
-      // ---- start the next step of the lanes that continue or just got a photon ----
-      if (start) {
-        sd = begin_step(p, a, pid);
-        b = Best{fminf(sd.d_abs, sd.d_sca), -1, -1};
-        ray = make_ray(p.pos, p.dir, a.n_tris);
-        const float tiny = 1e-30f;
-        inv = f3{1.0f / (fabsf(p.dir.x) > tiny ? p.dir.x : copysignf(tiny, p.dir.x)),
-                 1.0f / (fabsf(p.dir.y) > tiny ? p.dir.y : copysignf(tiny, p.dir.y)),
-                 1.0f / (fabsf(p.dir.z) > tiny ? p.dir.z : copysignf(tiny, p.dir.z))};
-        oi = f3{p.pos.x * inv.x, p.pos.y * inv.y, p.pos.z * inv.z};
-        node = 0;
-        leaf = -1;
-        stack.sp = 0;
-        stack.base = 0;
-        if (kCount) n_steps++;
-        // no triangle is closer than the cell's safety distance: a shorter free
-        // path cannot reach one, and the search's answer is "no hit"
-        if (b.t < safety_at(a, p.pos)) {
-          state = kWaiting;
-          if (kCount) cnt.skipped++;
-        }
-      }
-    }
-    // ---- one micro-step of every traversing lane's closest-hit search ----
-    if (kCount) {
-      const unsigned long long t_now = clock64();
-      cyc_phase += t_now - t_mark;
-      t_mark = t_now;
-      cnt.slots++;
-    }
-    // A micro-step tests at most one triangle and then visits at most one node:
-    // when the wave's lanes are split between the two kinds of work it pays for
-    // both either way, so a lane holding a leaf and a node does both.  The
-    // closest hit does not depend on the order in which candidates are tested.
-    if (state == kTraversing) {
-      if (kCount) cnt.busy++;
-      if (leaf < 0 && node < 0 && stack.sp > 0) {
-        const int32_t e = stack.pop();
-        if (e >= 0) node = e; else leaf = ~e;
-      }
-      if (leaf >= 0) {
-        // one triangle per micro-step: the packed leaf advances to its next triangle
-        const int32_t k = leaf >> 3, rest = leaf & 7;
-        if (kCount) cnt.tris++;
-        test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
-        leaf = rest > 0 ? (((k + 1) << 3) | (rest - 1)) : -1;
-      }
-      if (leaf < 0 && node < 0 && stack.sp > 0) {
-        const int32_t e = stack.pop();
-        if (e >= 0) node = e; else leaf = ~e;
-      }
-      if (node >= 0) {
-        if (!visit_node<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf,
-                                cnt)) {
-          b.tri = kTraversalFailed;
-          state = kWaiting;
-        }
-      }
-      // search complete: b holds the closest hit (or none)
-      if (state == kTraversing && leaf < 0 && node < 0 && stack.sp == 0) state = kWaiting;
-    }
-    if (kCount) cyc_search += clock64() - t_mark;
-  }
-
-  // ---- per-wave reductions at exit ----
-  if (kMode == kBackward) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double s = wave_sum(acc[q]);
-      if (lane == 0 && s != 0.0) atomicAdd(a.grad_params + q, s);
-    }
-  }
-  if (kCount) {
-    const unsigned long long s9 = wave_sum_u64(n_steps);
-    const unsigned long long s10 = wave_sum_u64(cnt.nodes);
-    const unsigned long long s11 = wave_sum_u64(cnt.tris);
-    const unsigned long long s12 = wave_sum_u64(cnt.slots);
-    const unsigned long long s13 = wave_sum_u64(cnt.busy);
-    const unsigned long long s14 = wave_sum_u64(cnt.skipped);
-    if (lane == 0) {
-      atomicAdd(&blk_stats[9], s9);
-      atomicAdd(&blk_stats[10], s10);
-      atomicAdd(&blk_stats[11], s11);
-      atomicAdd(&blk_stats[12], s12);
-      atomicAdd(&blk_stats[13], s13);
-      atomicAdd(&blk_stats[14], s14);
-      atomicAdd(&blk_stats[15], n_phases);
-      atomicAdd(&blk_stats[16], cyc_phase);
-      atomicAdd(&blk_stats[17], cyc_search);
-    }
-    __syncthreads();
-    if (threadIdx.x < 18 && a.stats) atomicAdd(a.stats + threadIdx.x, blk_stats[threadIdx.x]);
-  }
-}
 
 __global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
 
@@ -1261,9 +156,10 @@ hipError_t launch_one(const LaunchArgs& a, int block, int grid, size_t lds, hipS
 
 }  // namespace
 
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block) {
-  return size_t(n_lds_nodes) * sizeof(Node4) + size_t(stack_lds) * block * 4 +
-         kStatsWords * sizeof(unsigned long long);
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, int32_t tally_cells,
+                           bool grad) {
+  return tally_lds_bytes(tally_cells, grad) + size_t(n_lds_nodes) * sizeof(Node4) +
+         size_t(stack_lds) * block * 4 + kStatsWords * sizeof(unsigned long long);
 }
 
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
@@ -1273,11 +169,16 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
 
 hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
                             int block, int grid, hipStream_t s) {
-  const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block);
+  // block tallies only in the plain forward launch (no records, no counters)
+  const bool tally = mode == kForward && a.tally_cells > 0 && !records && !count;
+  const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block,
+                                         tally ? a.tally_cells : 0, grad);
   if (mode == kBackward) {
     if (records || count || grad) return hipErrorInvalidValue;
     return launch_one<kBackward, false, false, false>(a, block, grid, lds, s);
   }
+  if (mode != kForward) return hipErrorInvalidValue;
+  if (tally) return launch_propagate_tally(a, grad, block, grid, lds, s);
   const int key = (grad ? 4 : 0) | (records ? 2 : 0) | (count ? 1 : 0);
   switch (key) {
     case 0: return launch_one<kForward, false, false, false>(a, block, grid, lds, s);
@@ -1291,7 +192,8 @@ hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool recor
   }
 }
 
-hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, int* out) {
+hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, bool tally, int* out) {
+  if (tally) return max_blocks_per_cu_tally(block, lds_bytes, out);
   if (count)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
         out, reinterpret_cast<const void*>(propagate_kernel<kForward, true, true, true>), block,

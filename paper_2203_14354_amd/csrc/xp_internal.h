@@ -19,6 +19,8 @@ constexpr int kStatsWords = 24;
 constexpr int kStackLds = 16;        // LDS ring entries per lane
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
+constexpr size_t kMaxTallyBytes = 16384;  // LDS per workgroup for pre-summed tallies
+constexpr int64_t kAutoTallyCells = 64;   // default: pre-sum tallies of at most this many cells
 
 // 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
 // reads the node with seven 16-byte loads.  child[i] is the traversal stack
@@ -72,7 +74,10 @@ struct DevDispersion {
   float inv_abs[kMaxDispersion], inv_ray[kMaxDispersion];
 };
 
-enum Mode : int32_t { kForward = 0, kBackward = 1 };
+// kForwardTally: the forward transport with its hit-map and gradient tallies
+// pre-summed per workgroup in LDS (a separate instantiation, so the plain
+// forward kernel carries none of its registers)
+enum Mode : int32_t { kForward = 0, kBackward = 1, kForwardTally = 2 };
 
 // Everything a propagate launch needs, passed by value (kernel arguments).
 struct LaunchArgs {
@@ -130,6 +135,7 @@ struct LaunchArgs {
   DevMaterial mats[kMaxMaterials];
   DevSurface surfs[kMaxSurfaces];
   DevDispersion disp[kMaxMaterials];
+  int32_t tally_cells;     // cells of the LDS tallies (kForwardTally launches)
 };
 
 // Per-cell lower bound of the distance to the nearest triangle (see safety.cpp).
@@ -162,7 +168,17 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
 hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
                             int block, int grid, hipStream_t s);
-hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, int* out);
+hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, bool tally, int* out);
+// the kForwardTally variants (compiled apart, in propagate_tally.hip)
+hipError_t launch_propagate_tally(const LaunchArgs& a, bool grad, int block, int grid, size_t lds,
+                                  hipStream_t s);
+hipError_t max_blocks_per_cu_tally(int block, size_t lds_bytes, int* out);
+// LDS bytes of the per-workgroup tallies (a multiple of 16)
+__host__ __device__ inline size_t tally_lds_bytes(int32_t cells, bool grad) {
+  return cells > 0 ? (size_t(cells) * (grad ? 40 : 4) + 15) & ~size_t(15) : 0;
+}
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, int32_t tally_cells,
+                           bool grad);
 hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_tris,
                               int32_t stack_depth, int64_t n, const float* orig, const float* dir,
                               const int32_t* skip, float tmin, float tmax, int32_t brute,

@@ -1,6 +1,7 @@
 """Gradient tallies on the GPU: per-photon scores against the oracle, the
 backward replay against the contraction of the fused Jacobian, the analytic
 sphere, and common-random-number finite differences."""
+import dataclasses
 import math
 
 import numpy as np
@@ -144,3 +145,39 @@ def test_crn_finite_differences(rt, p, h):
     sc = G[:, p]
     se = math.sqrt(fd.var(ddof=1) / nb + sc.var(ddof=1) / nb)
     assert abs(fd.mean() - sc.mean()) < 4 * se + 0.02 * abs(sc.mean()), (fd.mean(), sc.mean(), se)
+
+
+def test_block_tallies_equal_global_tallies(rt):
+    """A launch with few hit-map cells can sum its hits and gradient scores per
+    workgroup in LDS and add them to global memory once per workgroup
+    (block_tally = 1), or add every detection to global memory directly
+    (block_tally = -1).  Both follow the same photons: hits identical,
+    gradients equal up to summation order.  With one event per source (300 x
+    38 cells, too many for LDS) the tallies always go to global memory, and
+    summed over the sources they equal the single-event tallies."""
+    wl = W.differentiable(n_points=300, photons_per_point=2_000)
+    det = rt.Detector(wl.mesh, device=0)
+    per = dataclasses.replace(wl.sources, per_source_events=True)
+    for grad in (False, True):
+        a = det.propagate(wl.sources, seed=5, grad=grad, launch={"block_tally": 1})
+        c = det.propagate(wl.sources, seed=5, grad=grad, launch={"block_tally": -1})
+        b = det.propagate(per, seed=5, grad=grad, launch={"block_tally": 1})
+        torch.cuda.synchronize()
+        assert a["hit_map"].shape == (1, det.n_channels) and b["hit_map"].shape == (300, det.n_channels)
+        assert torch.equal(a["hit_map"], c["hit_map"])
+        assert torch.equal(a["hit_map"][0], b["hit_map"].sum(dim=0))
+        assert int(a["hit_map"].sum()) > 100_000
+        if grad:
+            ga = a["grad"][0].cpu().numpy()
+            for other in (c["grad"][0], b["grad"].sum(dim=0)):
+                assert np.allclose(ga, other.cpu().numpy(), rtol=1e-10, atol=1e-12 * np.abs(ga).max())
+
+
+def test_block_tally_config_is_validated(rt):
+    from paper_2203_14354_amd._lib import XpError
+    wl = W.differentiable(n_points=2, photons_per_point=100)
+    det = rt.Detector(wl.mesh, device=0)
+    with pytest.raises(XpError):
+        det.propagate(wl.sources, seed=0, launch={"block_tally": 2})
+    cfg = det.autotune(wl.sources, sample_photons=50_000)
+    assert cfg["block_tally"] in (-1, 1)
