@@ -175,7 +175,8 @@ def main():
         "config": {"workload": "darwin_tpc", "photons_per_step": N,
                    "triangles": int(mesh.n_triangles), "sensors": int(mesh.n_sensors),
                    "source": "uniform in r<=1.299 m, -2.597<=z<=-0.001 m, isotropic, 175 nm",
-                   "bvh_nodes": det.bvh["n_nodes"], "bvh_depth": det.bvh["depth"],
+                   "bvh_nodes": det.bvh["n_nodes"], "bvh_references": det.bvh["n_references"],
+                   "bvh_depth": det.bvh["depth"],
                    "bvh_max_stack": det.bvh["max_stack"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -183,18 +183,28 @@ typedef struct xp_bvh_options {
                               0..512 (0 = no grid, also when opts is NULL).  A step whose free
                               path is shorter than the grid's distance bound skips the
                               closest-hit search; results are identical either way */
+  float split_budget;      /* triangles whose box is more than twice the least box a planar
+                              piece of their area and orientation needs (long slivers,
+                              fans) are clipped into pieces with tighter boxes, the most
+                              wasted box area first, adding at most this fraction of the
+                              triangle count as extra references, 0..4 (0 = default 0.02;
+                              negative = no splitting).  Every piece refers to the whole
+                              triangle: results are identical either way */
 } xp_bvh_options;
 
 typedef struct xp_bvh_stats {
   int64_t n_nodes;         /* 4-wide nodes of 128 bytes */
-  int64_t n_triangles;     /* triangles; stored as 48-byte records in three copies, one
-                              per dominant ray axis (triangle_bytes = 3 * 48 * n) */
+  int64_t n_triangles;     /* triangles of the mesh; stored as 48-byte records, one per
+                              reference, in three copies (one per dominant ray axis) */
   int32_t depth;           /* levels below the root */
   int32_t max_stack;       /* worst-case traversal stack entries */
   int64_t node_bytes, triangle_bytes;
   double build_seconds;
   int32_t safety_dims[3];  /* safety grid cells per axis (0 = no grid) */
   float safety_cell;       /* cell size (m) */
+  int64_t n_references;    /* triangle references in the leaves (n_triangles plus the
+                              extra pieces of split triangles); the records are stored per
+                              reference: triangle_bytes = 3 * 48 * n_references */
 } xp_bvh_info;
 
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload

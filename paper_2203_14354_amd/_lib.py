@@ -45,7 +45,7 @@ class Surface(ctypes.Structure):
 
 class BvhOptions(ctypes.Structure):
     _fields_ = [("max_leaf_size", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
-                ("safety_cells", ctypes.c_int32)]
+                ("safety_cells", ctypes.c_int32), ("split_budget", ctypes.c_float)]
 
 
 class BvhInfo(ctypes.Structure):
@@ -53,7 +53,7 @@ class BvhInfo(ctypes.Structure):
                 ("depth", ctypes.c_int32), ("max_stack", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int64), ("triangle_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("safety_dims", ctypes.c_int32 * 3),
-                ("safety_cell", ctypes.c_float)]
+                ("safety_cell", ctypes.c_float), ("n_references", ctypes.c_int64)]
 
 
 class Sources(ctypes.Structure):

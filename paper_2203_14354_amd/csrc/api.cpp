@@ -199,7 +199,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   std::memset(&a, 0, sizeof(a));
   a.nodes = ctx->d_nodes;
   a.tris = ctx->d_tris;
-  a.n_tris = int32_t(ctx->stats.n_triangles);
+  a.n_tris = int32_t(ctx->stats.n_references);
   a.channel_of_sensor = ctx->d_channel;
   const int levels = std::min<int>(lc.lds_levels, int(ctx->bvh.level_end.size()));
   a.n_lds_nodes = levels > 0 ? ctx->bvh.level_end[levels - 1] : 0;
@@ -279,7 +279,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.surfs[i].film_n = s.film_n;
     a.surfs[i].two_pi_d = float(2.0 * 3.14159265358979323846 * double(s.film_thickness_nm));
   }
-  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size, 0, false);
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size, 0);
   if (lds > ctx->max_lds)
     return fail(ctx, XP_ERR_UNSUPPORTED, "LDS request of " + std::to_string(lds) +
                                              " bytes exceeds the device limit; use fewer lds_levels "
@@ -295,28 +295,62 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   return XP_OK;
 }
 
-// Choose the per-workgroup LDS tallies of a forward launch (a.tally_cells):
-// they remove the atomic contention of small hit maps, which every photon of
-// a short-path detector hits; launches with records or counters, tallies too
-// large for LDS, or a lower occupancy keep the device-memory atomics.
+// Choose the per-workgroup LDS tallies of a forward launch: they remove the
+// atomic contention of tables whose few cells are hit by photons from every
+// workgroup at once: small hit maps (every detection of a short-path
+// detector), the loss table (every photon's end) and the arrival-time
+// histogram (every detection).  The hit map goes to LDS for at most
+// kAutoTallyCells cells (any size that fits with block_tally 1), the other
+// two whenever they fit.  Launches with records or counters, block_tally -1,
+// or tallies that would lower the occupancy keep the device-memory atomics.
+// Expects a.time_hist / a.loss and their sizes to be set.
 void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_launch_cfg& cfg,
                         bool hits, bool grad, bool records, bool count, xp::LaunchArgs& a) {
   a.tally_cells = 0;
-  if (cfg.block_tally < 0 || (!hits && !grad) || records || count) return;
+  a.tally_bytes = 0;
+  a.lds_time_off = a.lds_loss_off = -1;
+  a.n_time_cells = a.n_loss_cells = 0;
+  if (cfg.block_tally < 0 || records || count) return;
   const int64_t n_events =
       (src->kind == XP_SRC_POINTS && src->per_source_events) ? src->n_sources : 1;
+  size_t bytes = 0;
   const int64_t cells = n_events * int64_t(ctx->n_channels);
-  if (cells <= 0 || cells > (cfg.block_tally > 0 ? int64_t(INT32_MAX) : xp::kAutoTallyCells))
-    return;
-  const size_t bytes = xp::tally_lds_bytes(int32_t(std::min<int64_t>(cells, 1 << 20)), grad);
-  if (bytes > xp::kMaxTallyBytes) return;
-  const size_t lds =
-      xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, cfg.block_size, int32_t(cells), grad);
+  if ((hits || grad) && cells > 0 &&
+      cells <= (cfg.block_tally > 0 ? int64_t(1) << 20 : xp::kAutoTallyCells)) {
+    const size_t b = xp::tally_lds_bytes(int32_t(cells), grad);
+    if (b <= xp::kMaxTallyBytes) {
+      a.tally_cells = int32_t(cells);
+      bytes = b;
+    }
+  }
+  if (a.loss) {
+    const int64_t n = (int64_t(a.n_groups) + int64_t(ctx->mats.size())) * 8;
+    if (size_t(n) * 8 <= xp::kMaxLossTallyBytes) {
+      a.lds_loss_off = int32_t(bytes);
+      a.n_loss_cells = int32_t(n);
+      bytes += (size_t(n) * 8 + 15) & ~size_t(15);
+    }
+  }
+  if (a.time_hist) {
+    const int64_t n = n_events * int64_t(a.n_time_bins);
+    if (size_t(n) * 4 <= xp::kMaxTimeTallyBytes) {
+      a.lds_time_off = int32_t(bytes);
+      a.n_time_cells = int32_t(n);
+      bytes += (size_t(n) * 4 + 15) & ~size_t(15);
+    }
+  }
+  if (bytes == 0) return;
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, cfg.block_size, bytes);
   int per_cu = 0;
   if (lds <= ctx->max_lds &&
       xp::max_blocks_per_cu(cfg.block_size, lds, false, true, &per_cu) == hipSuccess &&
-      per_cu >= cfg.blocks_per_cu)
-    a.tally_cells = int32_t(cells);
+      per_cu >= cfg.blocks_per_cu) {
+    a.tally_bytes = int32_t(bytes);
+    return;
+  }
+  a.tally_cells = 0;  // does not fit: every table to device memory
+  a.lds_time_off = a.lds_loss_off = -1;
+  a.n_time_cells = a.n_loss_cells = 0;
 }
 
 int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records, bool count,
@@ -559,6 +593,9 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
   const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
   const int scells = opts ? opts->safety_cells : 0;
+  const float sb = opts ? opts->split_budget : 0.0f;
+  if (!(sb <= 4.0f)) return fail(ctx, XP_ERR_INVALID_ARG, "split_budget must be at most 4");
+  const double split_budget = sb == 0.0f ? xp::kDefaultSplitBudget : (sb < 0.0f ? 0.0 : double(sb));
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
   if (scells < 0 || scells > 512)
@@ -573,7 +610,8 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     std::string err;
     const int64_t nt = int64_t(ctx->mat_in.size());
     if (!xp::build_bvh4(ctx->vtx.data(), ctx->tri.data(), nt, ctx->mat_in.data(),
-                        ctx->mat_out.data(), ctx->surf.data(), ctx->sensor.data(), leaf, bins, r, err))
+                        ctx->mat_out.data(), ctx->surf.data(), ctx->sensor.data(), leaf, bins,
+                        split_budget, r, err))
       return fail(ctx, XP_ERR_MESH, err);
     if (r.max_stack > 512) return fail(ctx, XP_ERR_UNSUPPORTED, "BVH too deep");
     xp::SafetyGrid sg;
@@ -617,6 +655,7 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     ctx->stats.n_nodes = int64_t(r.nodes.size());
     ctx->stats.n_triangles = nt;
+    ctx->stats.n_references = r.n_refs;
     ctx->stats.depth = r.depth;
     ctx->stats.max_stack = r.max_stack;
     ctx->stats.node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
@@ -915,7 +954,7 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
   int32_t depth_pow2 = 1;
   while (depth_pow2 < ctx->bvh.max_stack + 4) depth_pow2 <<= 1;
   const hipError_t e = xp::launch_closest_hit(
-      ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_triangles), depth_pow2, n, orig, dir,
+      ctx->d_nodes, ctx->d_tris, int32_t(ctx->stats.n_references), depth_pow2, n, orig, dir,
       skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(closest_hit)");
   return XP_OK;

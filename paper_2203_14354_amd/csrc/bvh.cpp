@@ -6,11 +6,22 @@
 // 4-wide nodes whose child boxes fill one 128-byte cache line, laid out
 // breadth-first so that the top levels are a prefix of the node array and can
 // be staged in LDS with one contiguous copy.
+//
+// Before the build, triangles whose bounding box is much larger than the
+// triangle itself (long slivers, such as the wedges of a disk triangulated as
+// a fan from its centre) are pre-split into several references with tighter
+// boxes (early split clipping: Ernst and Woop, "Early split clipping for
+// bounding volume hierarchies", 2007; the worst boxes first, under a budget of
+// extra references, in the spirit of Karras and Aila, "Fast parallel
+// construction of high-quality bounding volume hierarchies", 2013).  Every
+// reference stores the whole triangle and its id, so the closest hit, and with
+// it every result, is the same with or without splitting.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <limits>
+#include <queue>
 
 #include "xp_internal.h"
 
@@ -44,6 +55,95 @@ struct Box {
   }
 };
 
+// ---- reference pre-splitting ----
+
+constexpr int kMaxSplitDepth = 10;    // at most 2^10 pieces per triangle
+constexpr double kSplitWasteRatio = 2.0;  // split while box area > ratio * ideal area
+
+float round_down(double x) {
+  float f = float(x);
+  return double(f) > x ? std::nextafter(f, -std::numeric_limits<float>::infinity()) : f;
+}
+float round_up(double x) {
+  float f = float(x);
+  return double(f) < x ? std::nextafter(f, std::numeric_limits<float>::infinity()) : f;
+}
+
+struct Poly {
+  int n = 0;
+  double v[3 + 2 * 6][3];  // a triangle clipped by at most six planes
+};
+
+// Clip a convex polygon to {x[axis] <= c} (keep_below) or {x[axis] >= c}.
+Poly clip(const Poly& in, int axis, double c, bool keep_below) {
+  Poly out;
+  for (int i = 0; i < in.n; ++i) {
+    const double* p = in.v[i];
+    const double* q = in.v[(i + 1) % in.n];
+    const double dp = keep_below ? c - p[axis] : p[axis] - c;
+    const double dq = keep_below ? c - q[axis] : q[axis] - c;
+    if (dp >= 0.0) std::memcpy(out.v[out.n++], p, sizeof(out.v[0]));
+    if ((dp > 0.0 && dq < 0.0) || (dp < 0.0 && dq > 0.0)) {
+      const double s = dp / (dp - dq);
+      double* r = out.v[out.n++];
+      for (int k = 0; k < 3; ++k) r[k] = p[k] + s * (q[k] - p[k]);
+      r[axis] = c;
+    }
+  }
+  return out;
+}
+
+struct Piece {
+  double cell_lo[3], cell_hi[3];  // the region of the triangle this reference covers
+  float lo[3], hi[3];             // its bounds, rounded outward
+  double waste;                   // box area above the ideal one
+  int32_t tri, depth;
+  bool operator<(const Piece& o) const { return waste < o.waste; }
+};
+
+// The part of triangle t inside the cell, its outward-rounded bounds and its
+// wasted box area: a planar piece of area A and unit normal n needs a box of
+// area at least 2 A (|nx| + |ny| + |nz|).  Returns false for an empty piece.
+bool make_piece(const double tri[3][3], const double n_l1, Piece& pc) {
+  Poly poly;
+  poly.n = 3;
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) poly.v[j][k] = tri[j][k];
+  for (int k = 0; k < 3 && poly.n > 0; ++k) {
+    if (std::isfinite(pc.cell_lo[k])) poly = clip(poly, k, pc.cell_lo[k], false);
+    if (poly.n > 0 && std::isfinite(pc.cell_hi[k])) poly = clip(poly, k, pc.cell_hi[k], true);
+  }
+  if (poly.n < 3) return false;
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) lo[k] = hi[k] = poly.v[0][k];
+  for (int i = 1; i < poly.n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], poly.v[i][k]);
+      hi[k] = std::max(hi[k], poly.v[i][k]);
+    }
+  double cx = 0.0, cy = 0.0, cz = 0.0;  // polygon area from the fan of cross products
+  for (int i = 1; i + 1 < poly.n; ++i) {
+    const double* a = poly.v[0];
+    const double* b = poly.v[i];
+    const double* c = poly.v[i + 1];
+    const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    cx += u[1] * w[2] - u[2] * w[1];
+    cy += u[2] * w[0] - u[0] * w[2];
+    cz += u[0] * w[1] - u[1] * w[0];
+  }
+  const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+  for (int k = 0; k < 3; ++k) {
+    pc.lo[k] = round_down(lo[k]);
+    pc.hi[k] = round_up(hi[k]);
+  }
+  const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+  const double box_area = 2.0 * (dx * dy + dy * dz + dz * dx);
+  const double ideal = 2.0 * area * n_l1;
+  pc.waste = box_area > kSplitWasteRatio * ideal ? box_area - ideal : 0.0;
+  return true;
+}
+
 struct Node2 {
   Box box;
   int32_t left = -1, right = -1;  // inner: children
@@ -54,7 +154,7 @@ struct Node2 {
 
 bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t* mat_in,
                 const int32_t* mat_out, const int32_t* surface, const int32_t* sensor,
-                int max_leaf, int bins, BvhResult& out, std::string& err) {
+                int max_leaf, int bins, double split_budget, BvhResult& out, std::string& err) {
   if (nt <= 0) {
     err = "empty mesh";
     return false;
@@ -67,21 +167,110 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
     err = "max_leaf_size must be 1..8";
     return false;
   }
-  std::vector<Box> tb(nt);
-  std::vector<float> cen(3 * nt);
-  for (int64_t i = 0; i < nt; ++i) {
-    for (int j = 0; j < 3; ++j) tb[i].grow(vtx + 3 * int64_t(tri[3 * i + j]));
-    for (int k = 0; k < 3; ++k) cen[3 * i + k] = 0.5f * (tb[i].lo[k] + tb[i].hi[k]);
+  // ---- references: whole triangles, or pieces of the worst-fitting ones ----
+  std::vector<Box> tb;
+  std::vector<int32_t> ref_tri;
+  const int64_t budget = std::min<int64_t>(int64_t(split_budget * double(nt)),
+                                           int64_t(kMaxLeafFirst) - 1 - nt);
+  {
+    std::priority_queue<Piece> heap;
+    std::vector<Piece> done;
+    std::vector<double> n_l1(nt, 0.0);
+    auto corners = [&](int32_t t, double p[3][3]) {
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) p[j][k] = vtx[3 * int64_t(tri[3 * int64_t(t) + j]) + k];
+    };
+    tb.reserve(size_t(nt) + size_t(std::max<int64_t>(budget, 0)));
+    ref_tri.reserve(tb.capacity());
+    for (int64_t i = 0; i < nt; ++i) {
+      Box b;
+      for (int j = 0; j < 3; ++j) b.grow(vtx + 3 * int64_t(tri[3 * i + j]));
+      if (budget <= 0) {
+        tb.push_back(b);
+        ref_tri.push_back(int32_t(i));
+        continue;
+      }
+      double p[3][3];
+      corners(int32_t(i), p);
+      const double u[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+      const double w[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+      const double c[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                           u[0] * w[1] - u[1] * w[0]};
+      const double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+      Piece pc;
+      for (int k = 0; k < 3; ++k) {
+        pc.cell_lo[k] = -std::numeric_limits<double>::infinity();
+        pc.cell_hi[k] = std::numeric_limits<double>::infinity();
+      }
+      pc.tri = int32_t(i);
+      pc.depth = 0;
+      if (len > 0.0) n_l1[i] = (std::fabs(c[0]) + std::fabs(c[1]) + std::fabs(c[2])) / len;
+      if (len > 0.0 && make_piece(p, n_l1[i], pc) && pc.waste > 0.0) {
+        heap.push(pc);
+      } else {  // degenerate or well fitting: the whole triangle
+        tb.push_back(b);
+        ref_tri.push_back(int32_t(i));
+      }
+    }
+    int64_t extra = 0;
+    while (!heap.empty()) {
+      Piece pc = heap.top();
+      heap.pop();
+      if (extra >= budget || pc.depth >= kMaxSplitDepth || pc.waste <= 0.0) {
+        done.push_back(pc);
+        continue;
+      }
+      // halve the piece's bounds along their longest axis
+      int axis = 0;
+      for (int k = 1; k < 3; ++k)
+        if (double(pc.hi[k]) - pc.lo[k] > double(pc.hi[axis]) - pc.lo[axis]) axis = k;
+      const double mid = 0.5 * (double(pc.lo[axis]) + double(pc.hi[axis]));
+      double p[3][3];
+      corners(pc.tri, p);
+      Piece kid[2] = {pc, pc};
+      kid[0].cell_hi[axis] = std::min(pc.cell_hi[axis], mid);
+      kid[1].cell_lo[axis] = std::max(pc.cell_lo[axis], mid);
+      int made = 0;
+      for (Piece& k : kid) {
+        k.depth = pc.depth + 1;
+        if (make_piece(p, n_l1[pc.tri], k)) {
+          heap.push(k);
+          ++made;
+        }
+      }
+      if (made == 0) {  // cannot happen for a non-empty piece; keep it whole
+        done.push_back(pc);
+        continue;
+      }
+      extra += made - 1;
+    }
+    for (const Piece& pc : done) {
+      Box b;
+      for (int k = 0; k < 3; ++k) {
+        b.lo[k] = pc.lo[k];
+        b.hi[k] = pc.hi[k];
+      }
+      tb.push_back(b);
+      ref_tri.push_back(pc.tri);
+    }
   }
-  std::vector<int32_t> perm(nt);
-  for (int64_t i = 0; i < nt; ++i) perm[i] = int32_t(i);
+  const int64_t nr = int64_t(tb.size());
+  if (nr >= kMaxLeafFirst) {
+    err = "too many triangle references";
+    return false;
+  }
+  std::vector<float> cen(3 * nr);
+  for (int64_t i = 0; i < nr; ++i)
+    for (int k = 0; k < 3; ++k) cen[3 * i + k] = 0.5f * (tb[i].lo[k] + tb[i].hi[k]);
+  std::vector<int32_t> perm(nr);
+  for (int64_t i = 0; i < nr; ++i) perm[i] = int32_t(i);
 
   // ---- binned SAH binary tree ----
   std::vector<Node2> n2;
-  n2.reserve(2 * size_t(nt) / std::max(1, max_leaf) + 16);
+  n2.reserve(2 * size_t(nr) / std::max(1, max_leaf) + 16);
   n2.emplace_back();
   struct Work { int32_t node, first, count; };
-  std::vector<Work> work{{0, 0, int32_t(nt)}};
+  std::vector<Work> work{{0, 0, int32_t(nr)}};
   std::vector<Box> bin_box(bins);
   std::vector<int32_t> bin_cnt(bins);
   std::vector<double> right_cost(bins);
@@ -258,10 +447,11 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
   }
   out.max_stack = need[0] + 1;
 
-  // ---- triangle records in leaf order, three rotated copies ----
-  out.tris.resize(3 * nt);
-  for (int64_t i = 0; i < nt; ++i) {
-    const int32_t t = perm[i];
+  // ---- triangle records in leaf order (one per reference), three rotated copies ----
+  out.n_refs = nr;
+  out.tris.resize(3 * nr);
+  for (int64_t i = 0; i < nr; ++i) {
+    const int32_t t = ref_tri[perm[i]];
     const float* p0 = vtx + 3 * int64_t(tri[3 * int64_t(t)]);
     const float* p1 = vtx + 3 * int64_t(tri[3 * int64_t(t) + 1]);
     const float* p2 = vtx + 3 * int64_t(tri[3 * int64_t(t) + 2]);
@@ -279,7 +469,7 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
       std::memcpy(&r.a[3], &t, 4);
       std::memcpy(&r.b[3], &packed, 4);
       std::memcpy(&r.c[3], &sens, 4);
-      out.tris[((kz + 1) % 3) * nt + i] = r;
+      out.tris[((kz + 1) % 3) * nr + i] = r;
     }
   }
   return true;

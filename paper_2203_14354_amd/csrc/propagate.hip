@@ -156,10 +156,9 @@ hipError_t launch_one(const LaunchArgs& a, int block, int grid, size_t lds, hipS
 
 }  // namespace
 
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, int32_t tally_cells,
-                           bool grad) {
-  return tally_lds_bytes(tally_cells, grad) + size_t(n_lds_nodes) * sizeof(Node4) +
-         size_t(stack_lds) * block * 4 + kStatsWords * sizeof(unsigned long long);
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, size_t tally_bytes) {
+  return tally_bytes + size_t(n_lds_nodes) * sizeof(Node4) + size_t(stack_lds) * block * 4 +
+         kStatsWords * sizeof(unsigned long long);
 }
 
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
@@ -170,9 +169,9 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
 hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,
                             int block, int grid, hipStream_t s) {
   // block tallies only in the plain forward launch (no records, no counters)
-  const bool tally = mode == kForward && a.tally_cells > 0 && !records && !count;
+  const bool tally = mode == kForward && a.tally_bytes > 0 && !records && !count;
   const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block,
-                                         tally ? a.tally_cells : 0, grad);
+                                         tally ? size_t(a.tally_bytes) : 0);
   if (mode == kBackward) {
     if (records || count || grad) return hipErrorInvalidValue;
     return launch_one<kBackward, false, false, false>(a, block, grid, lds, s);

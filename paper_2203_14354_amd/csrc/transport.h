@@ -890,13 +890,16 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   constexpr bool kGradAcc = kGrad || kMode == kBackward;
   constexpr bool kFwd = kMode != kBackward;
   constexpr bool kTally = kMode == kForwardTally;
-  // Block tallies sit at the start of LDS (a constant base, so no register
-  // holds their address through the loop): per cell an int32 hit count, or
-  // with gradients 4 FP64 scores followed by the hit count (40 bytes).
+  // Block tallies sit at the start of LDS: the hit map first (a constant
+  // base, so no register holds its address through the loop; per cell an
+  // int32 hit count, or with gradients 4 FP64 scores followed by the hit
+  // count, 40 bytes), then the loss table and the arrival-time histogram at
+  // the byte offsets the host chose (negative: that table goes straight to
+  // device memory).
   constexpr int32_t kTallyStride = kGrad ? 40 : 4;
   constexpr int32_t kTallyHitOffset = kGrad ? 32 : 0;
   char* const tally = reinterpret_cast<char*>(lds);
-  float4* lds_nodes = kTally ? lds + tally_lds_bytes(a.tally_cells, kGrad) / 16 : lds;
+  float4* lds_nodes = kTally ? lds + a.tally_bytes / 16 : lds;
   int32_t* stack_base = reinterpret_cast<int32_t*>(lds_nodes + a.n_lds_nodes * 8);
   unsigned long long* blk_stats =
       reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
@@ -904,10 +907,9 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
   if (kCount)
     for (int32_t i = threadIdx.x; i < kStatsWords; i += blockDim.x) blk_stats[i] = 0ull;
-  if (kTally) {
-    const int32_t words = int32_t(tally_lds_bytes(a.tally_cells, kGrad) / 4);
-    for (int32_t i = threadIdx.x; i < words; i += blockDim.x) reinterpret_cast<int32_t*>(tally)[i] = 0;
-  }
+  if (kTally)
+    for (int32_t i = threadIdx.x; i < a.tally_bytes / 4; i += blockDim.x)
+      reinterpret_cast<int32_t*>(tally)[i] = 0;
   __syncthreads();
   const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   LaneStack stack{stack_base + threadIdx.x, int32_t(blockDim.x), a.stack_lds - 1,
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
               sc[3] = p.sum_inv_t;
             }
             if (kFwd) {
-              if (kTally) {
+              if (kTally && a.tally_cells > 0) {
                 // few cells that every workgroup hits: pre-summed in LDS and
                 // flushed once per workgroup at exit
                 char* const t = tally + int32_t(cell) * kTallyStride;
@@ -982,9 +984,13 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
                 const float f = p.time * a.time_inv_bin;
                 const int32_t bin = f < float(a.n_time_bins - 1) ? int32_t(fmaxf(f, 0.0f))
                                                                  : a.n_time_bins - 1;
-                atomicAdd(a.time_hist + int64_t(p.event) * a.n_time_bins + bin, 1);
+                if (kTally && a.lds_time_off >= 0)
+                  atomicAdd(reinterpret_cast<int32_t*>(tally + a.lds_time_off) +
+                                p.event * a.n_time_bins + bin, 1);
+                else
+                  atomicAdd(a.time_hist + int64_t(p.event) * a.n_time_bins + bin, 1);
               }
-              if (!kTally && kGrad && a.grad) {
+              if ((!kTally || a.tally_cells == 0) && kGrad && a.grad) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) atomicAdd(a.grad + cell * 4 + q, sc[q]);
               }
@@ -1000,7 +1006,11 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
             const bool on_surface = fl >= F_DETECT && fl <= F_SURFACE_ABSORB && p.last_tri >= 0;
             const int64_t row = on_surface ? int64_t(a.tri_group[p.last_tri])
                                            : int64_t(a.n_groups) + p.medium;
-            atomicAdd(a.loss + row * 8 + fl, 1ull);
+            if (kTally && a.lds_loss_off >= 0)
+              atomicAdd(reinterpret_cast<unsigned long long*>(tally + a.lds_loss_off) + row * 8 + fl,
+                        1ull);
+            else
+              atomicAdd(a.loss + row * 8 + fl, 1ull);
           }
           if (kRecords) {
             xp_photon_record& rec = a.records[idx];
@@ -1115,6 +1125,16 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   // ---- block tallies to global memory (every wave of the block has left the loop) ----
   if (kTally) {
     __syncthreads();
+    if (a.lds_time_off >= 0) {
+      const int32_t* h = reinterpret_cast<const int32_t*>(tally + a.lds_time_off);
+      for (int32_t i = threadIdx.x; i < a.n_time_cells; i += blockDim.x)
+        if (h[i] != 0) atomicAdd(a.time_hist + i, h[i]);
+    }
+    if (a.lds_loss_off >= 0) {
+      const unsigned long long* l = reinterpret_cast<const unsigned long long*>(tally + a.lds_loss_off);
+      for (int32_t i = threadIdx.x; i < a.n_loss_cells; i += blockDim.x)
+        if (l[i] != 0ull) atomicAdd(a.loss + i, l[i]);
+    }
     for (int32_t i = threadIdx.x; i < a.tally_cells; i += blockDim.x) {
       const char* t = tally + i * kTallyStride;
       const int32_t h = *reinterpret_cast<const int32_t*>(t + kTallyHitOffset);

@@ -19,7 +19,10 @@ constexpr int kStatsWords = 24;
 constexpr int kStackLds = 16;        // LDS ring entries per lane
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
+constexpr double kDefaultSplitBudget = 0.02;  // extra BVH references from pre-splitting
 constexpr size_t kMaxTallyBytes = 16384;  // LDS per workgroup for pre-summed tallies
+constexpr size_t kMaxTimeTallyBytes = 8192;   // time histograms up to this size go to LDS
+constexpr size_t kMaxLossTallyBytes = 4096;   // loss tables up to this size go to LDS
 constexpr int64_t kAutoTallyCells = 64;   // default: pre-sum tallies of at most this many cells
 
 // 4-wide BVH node, one 128-byte line: child boxes in SoA order so that a lane
@@ -84,7 +87,7 @@ struct LaunchArgs {
   const Node4* nodes;
   const TriRec* tris;
   const int32_t* channel_of_sensor;
-  int32_t n_tris;          // triangles (records per rotated copy)
+  int32_t n_tris;          // triangle references (records per rotated copy)
   int32_t n_lds_nodes;
   int32_t stack_lds;       // LDS ring entries per lane (power of two)
   int32_t stack_total;     // worst-case stack entries of the BVH
@@ -135,7 +138,13 @@ struct LaunchArgs {
   DevMaterial mats[kMaxMaterials];
   DevSurface surfs[kMaxSurfaces];
   DevDispersion disp[kMaxMaterials];
-  int32_t tally_cells;     // cells of the LDS tallies (kForwardTally launches)
+  // per-workgroup LDS tallies (kForwardTally launches)
+  int32_t tally_cells;     // hit-map (and gradient) cells summed in LDS, 0: device memory
+  int32_t tally_bytes;     // LDS bytes of all block tallies (a multiple of 16)
+  int32_t lds_time_off;    // byte offset of the time histogram in LDS, < 0: device memory
+  int32_t lds_loss_off;    // byte offset of the loss table in LDS, < 0: device memory
+  int32_t n_time_cells;    // events * time bins
+  int32_t n_loss_cells;    // (groups + materials) * 8
 };
 
 // Per-cell lower bound of the distance to the nearest triangle (see safety.cpp).
@@ -151,7 +160,8 @@ bool build_safety_grid(const float* vtx, const int32_t* tri, int64_t nt, int cel
 
 struct BvhResult {
   std::vector<Node4> nodes;
-  std::vector<TriRec> tris;        // 3 * n records: the three rotated copies
+  std::vector<TriRec> tris;        // 3 * n_refs records: the three rotated copies
+  int64_t n_refs = 0;              // triangle references (records per copy)
   int32_t depth = 0;
   int32_t max_stack = 0;
   std::vector<int32_t> level_end;  // level_end[l] = number of nodes in levels 0..l
@@ -162,7 +172,7 @@ struct BvhResult {
 // error message on failure.
 bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t* mat_in,
                 const int32_t* mat_out, const int32_t* surface, const int32_t* sensor,
-                int max_leaf, int bins, BvhResult& out, std::string& err);
+                int max_leaf, int bins, double split_budget, BvhResult& out, std::string& err);
 
 // Launch wrappers (defined in the kernel translation unit).
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
@@ -177,8 +187,7 @@ hipError_t max_blocks_per_cu_tally(int block, size_t lds_bytes, int* out);
 __host__ __device__ inline size_t tally_lds_bytes(int32_t cells, bool grad) {
   return cells > 0 ? (size_t(cells) * (grad ? 40 : 4) + 15) & ~size_t(15) : 0;
 }
-size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, int32_t tally_cells,
-                           bool grad);
+size_t propagate_lds_bytes(int32_t n_lds_nodes, int32_t stack_lds, int block, size_t tally_bytes);
 hipError_t launch_closest_hit(const Node4* nodes, const TriRec* tris, int32_t n_tris,
                               int32_t stack_depth, int64_t n, const float* orig, const float* dir,
                               const int32_t* skip, float tmin, float tmax, int32_t brute,

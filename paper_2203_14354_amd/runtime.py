@@ -73,7 +73,7 @@ class Detector:
     """A mesh + optical tables + BVH resident on one GPU."""
 
     def __init__(self, mesh, device=0, channel_of_sensor=None, n_channels=None,
-                 max_leaf_size=1, sah_bins=32, safety_cells=0):
+                 max_leaf_size=1, sah_bins=32, safety_cells=0, split_budget=0.0):
         self.lib = load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.mesh = mesh
@@ -91,7 +91,7 @@ class Detector:
         else:
             self.n_channels = int(max(mesh.n_sensors, int(mesh.sensor.max()) + 1, 1))
         check(self.lib.xp_build_bvh(self.ctx, ctypes.byref(
-            BvhOptions(max_leaf_size, sah_bins, safety_cells))), self.ctx)
+            BvhOptions(max_leaf_size, sah_bins, safety_cells, split_budget))), self.ctx)
         info = BvhInfo()
         check(self.lib.xp_bvh_stats(self.ctx, ctypes.byref(info)), self.ctx)
         self.bvh = {k: getattr(info, k) for k, _ in BvhInfo._fields_}

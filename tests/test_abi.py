@@ -50,7 +50,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.ExtraTallies) == 24
     assert ctypes.sizeof(_lib.RunParams) == 32
     assert ctypes.sizeof(_lib.LaunchCfg) == 28
-    assert ctypes.sizeof(_lib.BvhOptions) == 12
+    assert ctypes.sizeof(_lib.BvhOptions) == 16
+    assert ctypes.sizeof(_lib.BvhInfo) == 72
     assert _lib.RECORD_DTYPE.itemsize == 96
 
 

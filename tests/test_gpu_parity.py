@@ -71,15 +71,23 @@ def test_samplers_match_oracle(rt, kind):
     assert ok.mean() >= (0.9999 if kind == 2 else 1.0)
 
 
-@pytest.mark.parametrize("geom", ["tpc1", "darwin"])
-def test_closest_hit_bvh_equals_brute_force_and_oracle(rt, geom):
+@pytest.mark.parametrize("geom,split", [("tpc1", 0.0), ("darwin", 0.0), ("darwin", -1.0),
+                                        ("darwin", 1.0)])
+def test_closest_hit_bvh_equals_brute_force_and_oracle(rt, geom, split):
+    """split: the BVH's reference pre-splitting budget (0 default, -1 none, 1
+    heavy): split triangles appear in several leaves with clipped boxes, and the
+    closest hit must not change."""
     if geom == "tpc1":
         mesh = W.tpc1(plane=True)
         o = W.uniform_points_in_cylinder(40_000, 0.0999, -0.0999, 0.0999, 1)
     else:
         mesh = W.darwin()
         o = W.uniform_points_in_cylinder(4_000, 1.29, -2.69, 0.015, 1)
-    det = rt.Detector(mesh, device=0)
+    det = rt.Detector(mesh, device=0, split_budget=split)
+    if split >= 0.0 and geom == "darwin":
+        assert det.bvh["n_references"] > det.bvh["n_triangles"]
+    if split < 0.0:
+        assert det.bvh["n_references"] == det.bvh["n_triangles"]
     rng = np.random.default_rng(2)
     d = rng.normal(size=o.shape)
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
@@ -274,6 +282,33 @@ def test_bvh_leaf_size_does_not_change_results(rt):
         torch.cuda.synchronize()
         det.close()
     assert torch.equal(maps[0], maps[1]) and torch.equal(maps[0], maps[2])
+
+
+def test_bvh_reference_splitting_does_not_change_results(rt):
+    """Pre-split triangle references (none, the default budget, a heavy one)
+    give the same closest hits, hence identical photon histories: DARWIN hit
+    maps and every field of 200,000 photon records bit for bit.  Rays are
+    aimed at the liquid-gas interface and the caps, the fans of long wedge
+    triangles that the splitting cuts up, by the photons' own reflections."""
+    mesh = W.darwin()
+    src = W.darwin_tpc(n_photons=1_000_000, mesh=mesh).sources
+    maps, recs = [], []
+    for split in (-1.0, 0.0, 0.5):
+        det = rt.Detector(mesh, device=0, split_budget=split)
+        maps.append(det.propagate(src, seed=3)["hit_map"].clone())
+        recs.append(det.propagate(src, seed=3, records=True, n_photons=200_000)["records"].clone())
+        torch.cuda.synchronize()
+        det.close()
+    for k in (1, 2):
+        assert torch.equal(maps[0], maps[k])
+        assert torch.equal(recs[0], recs[k])
+
+
+def test_bvh_split_budget_is_validated(rt):
+    from paper_2203_14354_amd._lib import XpError
+    for bad in (4.5, float("nan"), float("inf")):
+        with pytest.raises(XpError):
+            rt.Detector(W.disk_box(), device=0, split_budget=bad)
 
 
 @pytest.mark.parametrize("geom", ["darwin", "tpc1"])

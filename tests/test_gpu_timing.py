@@ -140,6 +140,31 @@ def test_darwin_loss_table_and_time_histogram(rt):
     assert lt[:, 1].sum() == int(out["hit_map"].sum())
 
 
+def test_block_tallied_loss_and_time_equal_device_tallies(rt):
+    """Without records the loss table and the time histogram are summed per
+    workgroup in LDS and added to device memory once per workgroup; with
+    block_tally -1, or with records, every photon adds to device memory.  The
+    integer tables are identical, and equal those of the GPU's own records."""
+    mesh = W.darwin()
+    det = rt.Detector(mesh, device=0)
+    groups, names = W.loss_components(mesh)
+    det.set_loss_groups(groups, len(names))
+    src = W.with_scintillation(W.darwin_tpc(n_photons=400_000, mesh=mesh).sources)
+    kw = dict(seed=12, time_hist=2048, time_bin_ns=1.0, loss=True)
+    lds = det.propagate(src, **kw)
+    dev = det.propagate(src, launch={"block_tally": -1}, **kw)
+    rec = det.propagate(src, records=True, **kw)
+    torch.cuda.synchronize()
+    for k in ("hit_map", "time_hist", "loss"):
+        assert torch.equal(lds[k], dev[k]) and torch.equal(lds[k], rec[k]), k
+    g = to_records(rec["records"])
+    assert np.array_equal(lds["loss"].cpu().numpy(),
+                          oracle.loss_table(g, groups, len(names), len(mesh.materials)))
+    assert np.array_equal(lds["time_hist"].cpu().numpy(),
+                          oracle.time_histogram(g, 1, 2048, 1.0, time_dtype=np.float32))
+    assert int(lds["loss"].sum()) == 400_000
+
+
 def test_extra_tallies_do_not_change_results(rt):
     mesh = W.tpc1()
     det = rt.Detector(mesh, device=0)
