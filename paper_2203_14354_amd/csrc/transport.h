@@ -884,6 +884,8 @@ enum : int32_t { kEmpty = 0, kTraversing = 1, kWaiting = 2 };
 // Five waves per SIMD (at most 96 VGPRs): the lane state of the search and the
 // photon fits without spilling; six or more waves force spills that cost more
 // than the extra latency hiding gains.
+constexpr int kRefillMin = 4;  // empty lanes before a wave refills them
+
 template <int kMode, bool kGrad, bool kRecords, bool kCount>
 __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   extern __shared__ float4 lds[];
@@ -1031,7 +1033,11 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         }
       }
       // ---- refill empty lanes from the photon pool (wave-uniform control flow) ----
+      // Emission costs the whole wave its code path, so a wave refills once at
+      // least kRefillMin of its lanes are empty (all of them, when nothing else
+      // is left to run).
       uint64_t dead = __ballot(state == kEmpty);
+      if (__popcll(dead) < kRefillMin) dead = 0ull;
       while (dead != 0ull && !exhausted) {
         if (pool_next >= pool_end) {
           uint64_t base = 0;
