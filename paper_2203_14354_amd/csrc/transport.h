@@ -388,10 +388,11 @@ __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, i
   const float4 B = *reinterpret_cast<const float4*>(rec.b);
   const float4 C = *reinterpret_cast<const float4*>(rec.c);
   const int32_t id = __float_as_int(A.w);
-  if (id == skip) return;
   const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
   const float t = intersect(r, va, vb, vc);
-  if (!(t > tmin) || !(t <= b.t) || !(t < kInfF)) return;
+  // the skipped triangle is rejected only here: an early return on its id
+  // lets the compiler load the id alone first, a second memory round trip
+  if (id == skip || !(t > tmin) || !(t <= b.t) || !(t < kInfF)) return;
   if (t < b.t || b.tri < 0 || id < b.tri) {
     b.t = t;
     b.tri = id;
@@ -524,14 +525,13 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   for (int i = 3; i >= 0; --i) {
     const int32_t e = ent[i];
     const bool hit = key[i] != kInfF;
-    int32_t spill = kNone;
-    if (hit && e < 0) {  // leaf: the nearer one keeps the slot
-      if (leaf >= 0) spill = ~leaf;
-      leaf = ~e;
-    } else if (hit) {    // inner node: the nearer one is followed
-      if (node >= 0) spill = node;
-      node = e;
-    }
+    // the nearer leaf keeps the leaf slot, the nearer inner node is followed;
+    // the previous holder spills (selects only: branches here cost more)
+    const bool is_leaf = e < 0;
+    const int32_t held = is_leaf ? (leaf >= 0 ? ~leaf : kNone) : (node >= 0 ? node : kNone);
+    const int32_t spill = hit ? held : kNone;
+    leaf = hit && is_leaf ? ~e : leaf;
+    node = hit && !is_leaf ? e : node;
     st.put(npush, spill);  // a slot above the top: harmless when nothing spills
     npush += spill != kNone ? 1 : 0;
   }
