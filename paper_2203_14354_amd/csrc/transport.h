@@ -459,7 +459,11 @@ struct LaneStack {
       base = sp;
       return glob[int64_t(sp) * gstride];
     }
-    return lds[__mul24(sp & mask, stride)];
+    // read through an LDS-qualified pointer: with a generic one the compiler
+    // merges this read and the overflow read into one flat load through a
+    // selected address, which then waits for every outstanding memory access
+    typedef __attribute__((address_space(3))) const int32_t lds_int;
+    return *(lds_int*)(lds + __mul24(sp & mask, stride));
   }
 };
 
