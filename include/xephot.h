@@ -216,6 +216,31 @@ typedef struct xp_bvh_stats {
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);
 int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
 
+/* The same host BVH build without a device or a context, for inspecting and
+ * testing the structure the kernels traverse.  vtx / tri / nv / nt as in
+ * xp_load_mesh (geometric checks only; media, surfaces and sensors are taken
+ * as 0 / -1 / -1); opts as in xp_build_bvh (safety_cells is ignored).  Fills
+ * *info (build_seconds: this call; safety fields 0) and, when not NULL, copies
+ *   nodes    info->n_nodes 128-byte nodes, breadth-first, root first:
+ *            float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4] (child
+ *            boxes, padded outward by 2^-20 relative + 1e-7 m), int32 child[4]
+ *            (>= 0: inner node index; INT32_MIN: empty slot; else the
+ *            complement of a leaf's first << 3 | (count - 1), a range of
+ *            records), int32 reserved[4] (0);
+ *   records  3 * info->n_references 48-byte records in leaf order, in three
+ *            copies (copy c starts at record c * n_references and holds the
+ *            coordinates rotated to (k + 1, k + 2, k) mod 3 for the dominant
+ *            ray axis k = (c + 2) mod 3, so copy 0 is the mesh frame): float
+ *            v0[3], int32 triangle index, float v1[3], int32 packed media and
+ *            surface, float v2[3], int32 sensor id.
+ * nodes_capacity counts nodes, records_capacity records; a buffer too small
+ * gives XP_ERR_INVALID_ARG.  Call once with NULL buffers for the sizes.
+ * Errors: XP_ERR_INVALID_ARG, XP_ERR_MESH, XP_ERR_OOM, XP_ERR_UNSUPPORTED
+ * (xp_last_error(NULL)). */
+int xp_bvh_build_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                      const xp_bvh_options* opts, xp_bvh_info* info, void* nodes,
+                      int64_t nodes_capacity, void* records, int64_t records_capacity);
+
 /* ------------------------------------------------------------------------- */
 /* photon sources                                                             */
 /* ------------------------------------------------------------------------- */

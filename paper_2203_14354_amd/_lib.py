@@ -90,6 +90,14 @@ class LaunchCfg(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# the BVH as xp_bvh_build_host returns it: 128-byte nodes, 48-byte triangle records
+NODE_DTYPE = np.dtype([("lo_x", np.float32, 4), ("hi_x", np.float32, 4), ("lo_y", np.float32, 4),
+                       ("hi_y", np.float32, 4), ("lo_z", np.float32, 4), ("hi_z", np.float32, 4),
+                       ("child", np.int32, 4), ("reserved", np.int32, 4)])
+TRIREC_DTYPE = np.dtype([("v0", np.float32, 3), ("tri", np.int32), ("v1", np.float32, 3),
+                         ("packed", np.int32), ("v2", np.float32, 3), ("sensor", np.int32)])
+EMPTY_CHILD = -2 ** 31
+
 RECORD_DTYPE = np.dtype([
     ("flag", np.int32), ("last_tri", np.int32), ("sensor", np.int32), ("steps", np.int32),
     ("event", np.int32), ("medium", np.int32), ("n_scatter", np.int32), ("reserved", np.int32),
@@ -106,7 +114,7 @@ EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_
            "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
            "xp_sample_emission_time", "xp_sample_wavelength", "xp_surface_reflectance",
            "xp_stream_read",
-           "xp_safety_grid_host", "xp_version"]
+           "xp_safety_grid_host", "xp_bvh_build_host", "xp_version"]
 
 _lib = None
 
@@ -146,6 +154,7 @@ def load():
         "xp_stream_read": (ctypes.c_int, [P, I64, I32, I32, P, P]),
         "xp_surface_reflectance": (ctypes.c_int, [I32, F, F, F, F, F, F, I64, P, P, P, P]),
         "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
+        "xp_bvh_build_host": (ctypes.c_int, [P, I64, P, I64, P, P, P, I64, P, I64]),
         "xp_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -420,6 +420,48 @@ void xp_context_destroy(xp_context* ctx) {
   delete ctx;
 }
 
+// The geometric checks of a mesh: sizes, finite coordinates, vertex indices
+// in range, no degenerate triangle.
+int check_geometry(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* tri, int64_t nt) {
+  if (nv <= 0 || nt <= 0 || nt >= (int64_t(1) << 31) || nv >= (int64_t(1) << 31))
+    return fail(ctx, XP_ERR_INVALID_ARG, "nv and nt must be in [1, 2^31)");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(vtx[i]))
+      return fail(ctx, XP_ERR_MESH, "non-finite vertex coordinate at vertex " + std::to_string(i / 3));
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t* q = tri + 3 * t;
+    for (int k = 0; k < 3; ++k)
+      if (q[k] < 0 || q[k] >= nv)
+        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a vertex index out of range");
+    const float* p0 = vtx + 3 * int64_t(q[0]);
+    const float* p1 = vtx + 3 * int64_t(q[1]);
+    const float* p2 = vtx + 3 * int64_t(q[2]);
+    const double e1[3] = {double(p1[0]) - p0[0], double(p1[1]) - p0[1], double(p1[2]) - p0[2]};
+    const double e2[3] = {double(p2[0]) - p0[0], double(p2[1]) - p0[1], double(p2[2]) - p0[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) < 1e-12)
+      return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " is degenerate (area < 1e-12 m^2)");
+  }
+  return XP_OK;
+}
+
+// BVH build options with their defaults filled in.
+int parse_bvh_options(xp_context* ctx, const xp_bvh_options* opts, int& leaf, int& bins,
+                      int& scells, double& split_budget) {
+  leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
+  bins = opts && opts->sah_bins ? opts->sah_bins : 32;
+  scells = opts ? opts->safety_cells : 0;
+  const float sb = opts ? opts->split_budget : 0.0f;
+  if (!(sb <= 4.0f)) return fail(ctx, XP_ERR_INVALID_ARG, "split_budget must be at most 4");
+  split_budget = sb == 0.0f ? xp::kDefaultSplitBudget : (sb < 0.0f ? 0.0 : double(sb));
+  if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
+    return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
+  if (scells < 0 || scells > 512)
+    return fail(ctx, XP_ERR_INVALID_ARG, "safety_cells must be in 0..512");
+  return XP_OK;
+}
+
 int xp_load_mesh(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
                  const int32_t* mat_inner, const int32_t* mat_outer, const int32_t* surface,
                  const int32_t* sensor) {
@@ -427,26 +469,10 @@ int xp_load_mesh(xp_context* ctx, const float* vtx, int64_t nv, const int32_t* t
   try {
     if (!vtx || !tri || !mat_inner || !mat_outer || !surface || !sensor)
       return fail(ctx, XP_ERR_INVALID_ARG, "null mesh array");
-    if (nv <= 0 || nt <= 0 || nt >= (int64_t(1) << 31) || nv >= (int64_t(1) << 31))
-      return fail(ctx, XP_ERR_INVALID_ARG, "nv and nt must be in [1, 2^31)");
-    for (int64_t i = 0; i < 3 * nv; ++i)
-      if (!std::isfinite(vtx[i]))
-        return fail(ctx, XP_ERR_MESH, "non-finite vertex coordinate at vertex " + std::to_string(i / 3));
+    const int gc = check_geometry(ctx, vtx, nv, tri, nt);
+    if (gc != XP_OK) return gc;
     int32_t mm = -1, ms = -1, mse = -1;
     for (int64_t t = 0; t < nt; ++t) {
-      const int32_t* q = tri + 3 * t;
-      for (int k = 0; k < 3; ++k)
-        if (q[k] < 0 || q[k] >= nv)
-          return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a vertex index out of range");
-      const float* p0 = vtx + 3 * int64_t(q[0]);
-      const float* p1 = vtx + 3 * int64_t(q[1]);
-      const float* p2 = vtx + 3 * int64_t(q[2]);
-      const double e1[3] = {double(p1[0]) - p0[0], double(p1[1]) - p0[1], double(p1[2]) - p0[2]};
-      const double e2[3] = {double(p2[0]) - p0[0], double(p2[1]) - p0[1], double(p2[2]) - p0[2]};
-      const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
-                   cz = e1[0] * e2[1] - e1[1] * e2[0];
-      if (0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) < 1e-12)
-        return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " is degenerate (area < 1e-12 m^2)");
       if (mat_inner[t] < 0 || mat_inner[t] > 255 || mat_outer[t] < 0 || mat_outer[t] > 255)
         return fail(ctx, XP_ERR_MESH, "triangle " + std::to_string(t) + " has a material id outside [0, 255]");
       if (surface[t] < -1 || surface[t] > 65534)
@@ -590,16 +616,10 @@ int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
   if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
-  const int leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
-  const int bins = opts && opts->sah_bins ? opts->sah_bins : 32;
-  const int scells = opts ? opts->safety_cells : 0;
-  const float sb = opts ? opts->split_budget : 0.0f;
-  if (!(sb <= 4.0f)) return fail(ctx, XP_ERR_INVALID_ARG, "split_budget must be at most 4");
-  const double split_budget = sb == 0.0f ? xp::kDefaultSplitBudget : (sb < 0.0f ? 0.0 : double(sb));
-  if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
-    return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
-  if (scells < 0 || scells > 512)
-    return fail(ctx, XP_ERR_INVALID_ARG, "safety_cells must be in 0..512");
+  int leaf = 1, bins = 32, scells = 0;
+  double split_budget = 0.0;
+  const int oc = parse_bvh_options(ctx, opts, leaf, bins, scells, split_budget);
+  if (oc != XP_OK) return oc;
   if (int64_t(ctx->mat_in.size()) >= (int64_t(1) << 28))
     return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
   if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
@@ -674,6 +694,54 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     return fail(ctx, XP_ERR_OOM, "host allocation failed");
   } catch (...) {
     return fail(ctx, XP_ERR_HIP, "unexpected exception");
+  }
+}
+
+int xp_bvh_build_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
+                      const xp_bvh_options* opts, xp_bvh_info* info, void* nodes,
+                      int64_t nodes_capacity, void* records, int64_t records_capacity) {
+  if (!vtx || !tri || !info) return fail(nullptr, XP_ERR_INVALID_ARG, "null argument");
+  try {
+    int rc = check_geometry(nullptr, vtx, nv, tri, nt);
+    if (rc != XP_OK) return rc;
+    int leaf = 1, bins = 32, scells = 0;
+    double split_budget = 0.0;
+    rc = parse_bvh_options(nullptr, opts, leaf, bins, scells, split_budget);
+    if (rc != XP_OK) return rc;
+    if (nt >= (int64_t(1) << 28))
+      return fail(nullptr, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
+    const auto t0 = std::chrono::steady_clock::now();
+    const std::vector<int32_t> zero(size_t(nt), 0), none(size_t(nt), -1);
+    xp::BvhResult r;
+    std::string err;
+    if (!xp::build_bvh4(vtx, tri, nt, zero.data(), zero.data(), none.data(), none.data(), leaf,
+                        bins, split_budget, r, err))
+      return fail(nullptr, XP_ERR_MESH, err);
+    *info = xp_bvh_info{};
+    info->n_nodes = int64_t(r.nodes.size());
+    info->n_triangles = nt;
+    info->n_references = r.n_refs;
+    info->depth = r.depth;
+    info->max_stack = r.max_stack;
+    info->node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
+    info->triangle_bytes = int64_t(r.tris.size() * sizeof(xp::TriRec));
+    info->build_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (nodes) {
+      if (nodes_capacity < info->n_nodes)
+        return fail(nullptr, XP_ERR_INVALID_ARG, "node buffer too small");
+      std::memcpy(nodes, r.nodes.data(), r.nodes.size() * sizeof(xp::Node4));
+    }
+    if (records) {
+      if (records_capacity < int64_t(r.tris.size()))
+        return fail(nullptr, XP_ERR_INVALID_ARG, "record buffer too small");
+      std::memcpy(records, r.tris.data(), r.tris.size() * sizeof(xp::TriRec));
+    }
+    return XP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, XP_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(nullptr, XP_ERR_INVALID_ARG, "unexpected exception");
   }
 }
 

@@ -263,6 +263,24 @@ class Detector:
         return tri, t
 
 
+def bvh_build_host(vertices, triangles, max_leaf_size=1, sah_bins=32, split_budget=0.0):
+    """Build the BVH on the host only (xp_bvh_build_host; no device needed).
+    Returns (info dict, nodes as NODE_DTYPE, records as TRIREC_DTYPE)."""
+    lib = load()
+    v = np.ascontiguousarray(vertices, dtype=np.float32).reshape(-1, 3)
+    t = np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3)
+    opts = BvhOptions(max_leaf_size, sah_bins, 0, split_budget)
+    info = BvhInfo()
+    args = (_host_ptr(v), len(v), _host_ptr(t), len(t), ctypes.byref(opts), ctypes.byref(info))
+    check(lib.xp_bvh_build_host(*args, None, 0, None, 0))
+    nodes = np.zeros(info.n_nodes, dtype=_lib.NODE_DTYPE)
+    recs = np.zeros(3 * info.n_references, dtype=_lib.TRIREC_DTYPE)
+    check(lib.xp_bvh_build_host(*args, _host_ptr(nodes), len(nodes), _host_ptr(recs), len(recs)))
+    d = {k: getattr(info, k) for k, _ in BvhInfo._fields_}
+    d["safety_dims"] = list(info.safety_dims)
+    return d, nodes, recs
+
+
 def time_quantile(time_hist: torch.Tensor, time_bin_ns: float, q: float = 0.9, stream=None):
     """Per-event arrival-time quantile (q = 0.9: t90) of int32 time histograms
     [events, bins], computed on the device.  Returns float32 [events]."""
