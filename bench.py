@@ -158,6 +158,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras.update(gradient_overhead(torch, W, Detector, dev))
+        extras.update(gradient_overhead_darwin(torch, W, det, mesh, dev))
         extras.update(batched_vs_plain(torch, W, Detector, dev))
         extras.update(lce_map_rate(torch, W, dev))
         extras.update(arrival_time_and_losses(torch, W, Detector, mesh, det, dev, args.photons))
@@ -180,7 +181,8 @@ def main():
                    "bvh_max_stack": det.bvh["max_stack"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "per_launch": {"steps_per_photon": n_steps / N, "nodes_per_step": n_nodes / n_steps,
+        "per_launch": {"steps_per_photon": n_steps / N, "photon_steps_per_s": value * n_steps / N,
+                       "nodes_per_step": n_nodes / n_steps,
                        "triangles_per_step": n_tris / n_steps,
                        "detected_fraction": st[1] / N, "bulk_absorbed_fraction": st[4] / N,
                        "surface_absorbed_fraction": st[3] / N,
@@ -219,6 +221,32 @@ def gradient_overhead(torch, W, Detector, dev):
     n = wl.sources.n_photons
     return {"gradient_overhead": {
         "workload": "differentiable: small TPC + transparent plane, 1e7 photons",
+        "forward_photons_per_s": n / t["forward"],
+        "fused_tallies_over_forward": t["forward_fused_tallies"] / t["forward"],
+        "forward_plus_backward_over_forward": (t["forward"] + t["backward_replay"]) / t["forward"],
+        "backward_replay_over_forward": t["backward_replay"] / t["forward"]}}
+
+
+def gradient_overhead_darwin(torch, W, det, mesh, dev, n=20_000_000):
+    """The same ratios on the DARWIN-scale workload (2e7 photons; gradients
+    with respect to the LXe lengths, 1,778 channels x 4 FP64 scores)."""
+    ds = det.sources(W.darwin_tpc(n_photons=n, mesh=mesh).sources)
+    hm = torch.zeros((1, det.n_channels), dtype=torch.int32, device=dev)
+    g = torch.zeros((1, det.n_channels, 4), dtype=torch.float64, device=dev)
+    gh = torch.ones((1, det.n_channels), dtype=torch.float32, device=dev)
+    gp = torch.zeros(4, dtype=torch.float64, device=dev)
+    runs = {
+        "forward": lambda: det.propagate(ds, seed=2, hit_map=hm),
+        "forward_fused_tallies": lambda: det.propagate(ds, seed=2, hit_map=hm, grad=g),
+        "backward_replay": lambda: det.backward(ds, gh, seed=2, grad_params=gp),
+    }
+    t = {}
+    for k, fn in runs.items():
+        fn()
+        d, _ = timed_launches(fn, 3, torch)
+        t[k] = statistics.median(d)
+    return {"gradient_overhead_darwin": {
+        "workload": f"darwin_tpc, {n} photons, gradients for the LXe absorption and Rayleigh lengths",
         "forward_photons_per_s": n / t["forward"],
         "fused_tallies_over_forward": t["forward_fused_tallies"] / t["forward"],
         "forward_plus_backward_over_forward": (t["forward"] + t["backward_replay"]) / t["forward"],
