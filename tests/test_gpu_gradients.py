@@ -181,3 +181,33 @@ def test_block_tally_config_is_validated(rt):
         det.propagate(wl.sources, seed=0, launch={"block_tally": 2})
     cfg = det.autotune(wl.sources, sample_photons=50_000)
     assert cfg["block_tally"] in (-1, 1)
+
+
+def test_block_tallies_with_several_events(rt):
+    """Per-source events whose tallies fit LDS beside the traversal stacks
+    (10 events x 38 channels of hits; 2 events with FP64 scores; a 4-event
+    time histogram of 512 bins): summed per workgroup (block_tally 1) they
+    equal the device-memory tallies (block_tally -1), hits and times exactly,
+    gradients up to summation order."""
+    wl = W.differentiable(n_points=10, photons_per_point=30_000)
+    det = rt.Detector(wl.mesh, device=0)
+    ten = dataclasses.replace(wl.sources, per_source_events=True)
+    two = W.point_sources(wl.sources.positions[:2], count_per_source=100_000, per_source_events=True)
+    four = W.point_sources(wl.sources.positions[:4], count_per_source=30_000, per_source_events=True)
+    res = {}
+    for bt in (1, -1):
+        L = {"block_tally": bt}
+        res[bt] = (det.propagate(ten, seed=9, launch=L)["hit_map"],
+                   det.propagate(two, seed=9, grad=True, launch=L),
+                   det.propagate(four, seed=3, time_hist=512, time_bin_ns=0.25, launch=L))
+    torch.cuda.synchronize()
+    hm = res[1][0]
+    assert hm.shape == (10, det.n_channels) and torch.equal(hm, res[-1][0])
+    assert np.all(hm.sum(dim=1).cpu().numpy() > 1000)  # every event got its own photons
+    a, b = res[1][1], res[-1][1]
+    assert a["hit_map"].shape == (2, det.n_channels) and torch.equal(a["hit_map"], b["hit_map"])
+    ga, gb = a["grad"].cpu().numpy(), b["grad"].cpu().numpy()
+    assert np.allclose(ga, gb, rtol=1e-10, atol=1e-12 * np.abs(gb).max())
+    ta, tb = res[1][2]["time_hist"], res[-1][2]["time_hist"]
+    assert ta.shape == (4, 512) and torch.equal(ta, tb) and int(ta.sum()) > 4000
+    assert torch.equal(res[1][2]["hit_map"], res[-1][2]["hit_map"])
