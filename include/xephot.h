@@ -329,7 +329,9 @@ typedef struct xp_launch_cfg {
 } xp_launch_cfg;
 
 /* One per photon (indexed by the launch-local photon index), written when
- * requested.  96 bytes. */
+ * requested.  96 bytes.  The score inputs (n_scatter, path_len, sum_inv_r,
+ * sum_inv_t) are tracked only by launches that also tally gradients
+ * (d_grad != NULL); otherwise they are 0. */
 typedef struct xp_photon_record {
   int32_t flag, last_tri, sensor, steps;
   int32_t event, medium, n_scatter, reserved;

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2203_14354_amd import workloads as W
-from tests.gpu_common import agreement, to_records
+from tests.gpu_common import agreement, detected_scores as _scores, to_records
 from tests.helpers import face_average
 
 pytestmark = pytest.mark.gpu
@@ -21,20 +21,6 @@ def rt():
     assert torch.cuda.is_available()
     from paper_2203_14354_amd import runtime
     return runtime
-
-
-def _scores(rec, mats, gm=0):
-    # the tables reach the kernel in FP32
-    L_a = float(np.float32(mats[gm].abs_length))
-    L_r = float(np.float32(mats[gm].rayleigh_length))
-    det = (rec["flag"] & 0xFF) == 1
-    s = np.zeros((len(rec), 4))
-    L = rec["path_len"].astype(np.float64)
-    s[:, 0] = L / L_a ** 2
-    s[:, 1] = L / L_r ** 2 - rec["n_scatter"].astype(np.float64) / L_r
-    s[:, 2] = rec["sum_inv_r"].astype(np.float64)
-    s[:, 3] = rec["sum_inv_t"].astype(np.float64)
-    return s * det[:, None]
 
 
 def test_fused_tallies_match_records_and_oracle(rt):
