@@ -274,3 +274,45 @@ def test_host_build_rejects_bad_input():
     assert lib.xp_bvh_build_host(*args, None, 0, None, 0) == _lib.XP_OK
     small = np.zeros(info.n_nodes - 1, dtype=_lib.NODE_DTYPE)
     assert lib.xp_bvh_build_host(*args, small.ctypes.data_as(P), len(small), None, 0) != _lib.XP_OK
+
+
+@pytest.mark.parametrize("split", [-1.0, 0.0, 1.0, 4.0])
+def test_tiny_meshes(split):
+    """One sliver triangle and two, at every budget: at most budget x n extra
+    references, every point still covered, and the root of a one-leaf tree
+    holds the leaf."""
+    sliver = (np.array([[0, 0, 0], [3.0, 2.9, 0], [3.0, 3.0, 0.1]], np.float32),
+              np.array([[0, 1, 2]], np.int32))
+    pair = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [5, 5, 5]], np.float32),
+            np.array([[0, 1, 2], [1, 3, 2]], np.int32))
+    for v, t in (sliver, pair):
+        info, nodes, recs = R.bvh_build_host(v, t, split_budget=split)
+        nt, n = len(t), info["n_references"]
+        budget = 0.02 if split == 0.0 else max(split, 0.0)
+        assert nt <= n <= nt + int(budget * nt)
+        lo, hi, held = leaf_boxes(nodes, n)
+        assert np.all(held == 1)
+        ids = recs["tri"][:n]
+        assert np.array_equal(np.unique(ids), np.arange(nt))
+        rng = np.random.default_rng(0)
+        for k in range(nt):
+            P = rng.dirichlet([1, 1, 1], size=200) @ v[t[k]].astype(np.float64)
+            mine = np.nonzero(ids == k)[0]
+            ok = np.zeros(len(P), bool)
+            for r in mine:
+                ok |= np.all((P >= lo[r]) & (P <= hi[r]), axis=1)
+            assert ok.all()
+
+
+def test_split_depth_limit():
+    """A single long sliver with a budget far beyond what it can use stops at
+    the depth limit (at most 2^10 pieces) and stays covered."""
+    v = np.array([[0, 0, 0], [100.0, 99.9, 0], [100.0, 100.0, 0.01]], np.float32)
+    t = np.array([[0, 1, 2]], np.int32)
+    info, nodes, recs = R.bvh_build_host(v, t, split_budget=4.0)
+    assert info["n_references"] <= 5  # the budget: 4 x 1 triangle
+    v2 = np.concatenate([v, v + np.float32(200)])
+    t2 = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    info2, _, _ = R.bvh_build_host(v2, t2, split_budget=4.0)
+    assert info2["n_references"] <= 2 + 8
+    assert info2["max_stack"] >= info2["depth"]
