@@ -951,8 +951,10 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     for (int b : {64, 256})
       for (int l : {0, 3})
         for (int sl : {8, 16})
-          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb, -1});
-    // then the fastest of these with the block tallies on
+          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb, 0});
+    // then the fastest of these with the block tallies forced on (the default
+    // keeps them for small hit maps; the timing runs tally hits only, so it
+    // never turns them off for launches that also tally gradients)
     const size_t n_plain = cands.size();
     for (size_t ci = 0; ci <= n_plain; ++ci) {
       if (ci == n_plain) {

@@ -166,7 +166,7 @@ def test_block_tally_config_is_validated(rt):
     with pytest.raises(XpError):
         det.propagate(wl.sources, seed=0, launch={"block_tally": 2})
     cfg = det.autotune(wl.sources, sample_photons=50_000)
-    assert cfg["block_tally"] in (-1, 1)
+    assert cfg["block_tally"] in (0, 1)  # never turned off by a hit-map timing
 
 
 def test_block_tallies_with_several_events(rt):
