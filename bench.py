@@ -271,8 +271,16 @@ def batched_vs_plain(torch, W, Detector, dev):
     fp()
     db, _ = timed_launches(fb, 5, torch)
     dpl, _ = timed_launches(fp, 5, torch)
+    # the same launch autotuned and replayed from a captured HIP graph (the map
+    # is cleared by a fill kernel inside the graph)
+    from paper_2203_14354_amd.batched import BatchedRunner
+    runner = BatchedRunner(det, wl.sources, seed=2, autotune=True, use_graph=True)
+    runner.run()
+    dg, _ = timed_launches(runner.run, 5, torch)
     return {"batched_s1": {"workload": f"4096 log-normal sources, {n} photons, per-event maps",
                            "photons_per_s": n / statistics.median(db),
+                           "graph_autotuned_photons_per_s": n / statistics.median(dg),
+                           "autotuned_launch": runner.launch,
                            "plain_forward_photons_per_s": n / statistics.median(dpl)}}
 
 

@@ -426,12 +426,14 @@ int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
                 xp_stream stream);
 
 /* Pick the fastest launch configuration on a sample of `src` (at most
- * sample_photons photons) by timing hit-map launches: block sizes 64 / 256,
- * 0 / 3 BVH levels in LDS, 8 / 16 LDS stack entries, wave_batch 16 / 32 / 48
- * with the default block_tally, then the fastest of these with block_tally 1
- * (block_tally is never set to -1: the default keeps the LDS tallies that
- * gradient launches need).  Stores the result in the context (used when lc is
- * NULL) and in *out (may be NULL).  Integer results never depend on the
+ * sample_photons photons) by timing hit-map launches (best of three each):
+ * block sizes 64 / 256, 0 / 3 BVH levels in LDS, 8 / 16 LDS stack entries,
+ * wave_batch 16 / 32 / 48 with the default block_tally, then the fastest of
+ * these with block_tally 1 (block_tally is never set to -1: the default keeps
+ * the LDS tallies that gradient launches need).  The default configuration
+ * is kept unless a candidate is more than 2 % faster on the sample.  Stores
+ * the result in the context (used when lc is NULL) and in *out (may be
+ * NULL).  Integer results never depend on the
  * choice.  Synchronizes the stream.  Errors as xp_propagate. */
 int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
                 int64_t sample_photons, xp_launch_cfg* out, xp_stream stream);
