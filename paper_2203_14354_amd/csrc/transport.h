@@ -478,9 +478,10 @@ __device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t
   va = v;
 }
 
-// Visit one inner node: test its four child boxes, order the hits by entry
-// distance, follow the nearest inner child, postpone the nearest leaf (a leaf
-// the lane still holds is pushed) and push the rest far-first.  Stack
+// Visit one inner node: test its four child boxes, bring the nearest hit to
+// the front, then follow one inner child and hold one leaf (for the kind of
+// the nearest hit, that hit; for the other kind the first in node order; a
+// leaf the lane still holds is pushed) and push the other hits.  Stack
 // entries are node indices (>= 0) or complemented packed leaves
 // (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
 template <bool kCount>
@@ -515,12 +516,13 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
     key[i] = hit ? tn : kInfF;
     ent[i] = child[i];
   }
-  // ascending entry distance (a 5-comparator network); misses sort last
-  cswap(key[0], ent[0], key[1], ent[1]);
+  // one exchange pass brings the nearest hit to slot 0 (misses carry an
+  // infinite key); the others keep their node order.  A full sort (five
+  // exchanges) pops the pushed children in a slightly better order but costs
+  // more than the few extra visits it saves.
   cswap(key[2], ent[2], key[3], ent[3]);
-  cswap(key[0], ent[0], key[2], ent[2]);
-  cswap(key[1], ent[1], key[3], ent[3]);
   cswap(key[1], ent[1], key[2], ent[2]);
+  cswap(key[0], ent[0], key[1], ent[1]);
   node = -1;
   constexpr int32_t kNone = -1 - 0x7fffffff;
   st.reserve4();

@@ -6,9 +6,9 @@ reference splitting cut long triangles into pieces), the leaf ranges and the
 three rotated record copies are consistent, and the host's worst-case stack
 bound covers the traversal the kernel runs.  These tests check each on meshes
 with long fan wedges (the shape the splitting targets): the first two
-directly, the last by running the kernel's traversal order (children sorted by
-entry distance, nearest inner child followed, nearest leaf held, the rest
-pushed) in Python over random rays, and comparing its closest hits with a
+directly, the last by running the kernel's traversal order (one exchange
+pass brings the nearest child hit to the front, one inner child is followed
+and one leaf held, the rest pushed) in Python over random rays, and comparing its closest hits with a
 brute-force FP64 intersection of every triangle.
 """
 import numpy as np
@@ -199,13 +199,18 @@ def traverse(nodes, recs, n_refs, v, t, o, d):
             t0, t1 = (lo - o) * inv, (hi - o) * inv
         tn = np.nanmax(np.minimum(t0, t1), axis=1).clip(min=0.0)
         tf = np.minimum(np.nanmin(np.maximum(t0, t1), axis=1), best_t)
-        hits = [(tn[k], int(nd["child"][k])) for k in range(4)
-                if nd["child"][k] != _lib.EMPTY_CHILD and tn[k] <= tf[k]]
-        hits.sort(key=lambda h: h[0])
+        key = [tn[k] if nd["child"][k] != _lib.EMPTY_CHILD and tn[k] <= tf[k] else np.inf
+               for k in range(4)]
+        ent = [int(nd["child"][k]) for k in range(4)]
+        for a in (2, 1, 0):  # one exchange pass: the nearest hit to slot 0
+            if key[a + 1] < key[a]:
+                key[a], key[a + 1] = key[a + 1], key[a]
+                ent[a], ent[a + 1] = ent[a + 1], ent[a]
+        hits = [(key[k], ent[k]) for k in range(4) if key[k] != np.inf]
         node = None
         held = None
         pushes = []
-        for _, e in reversed(hits):  # far to near: the nearer one keeps the slot
+        for _, e in reversed(hits):  # slots 3..0: the later one keeps the slot
             if e < 0:
                 if held is not None:
                     pushes.append(held)
