@@ -223,7 +223,8 @@ int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
  * *info (build_seconds: this call; safety fields 0) and, when not NULL, copies
  *   nodes    info->n_nodes 128-byte nodes, breadth-first, root first:
  *            float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4] (child
- *            boxes, padded outward by 2^-20 relative + 1e-7 m), int32 child[4]
+ *            boxes, padded outward by 2^-20 relative + 1e-7 m; an empty slot
+ *            holds lo = +INFINITY, hi = -INFINITY), int32 child[4]
  *            (>= 0: inner node index; INT32_MIN: empty slot; else the
  *            complement of a leaf's first << 3 | (count - 1), a range of
  *            records), int32 reserved[4] (0);

@@ -394,9 +394,9 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
     }
     Node4 node;
     for (int k = 0; k < 4; ++k) {
-      if (k >= nk) {
-        node.lox[k] = node.loy[k] = node.loz[k] = 0.0f;
-        node.hix[k] = node.hiy[k] = node.hiz[k] = 0.0f;
+      if (k >= nk) {  // an inverted box: every slab test misses it
+        node.lox[k] = node.loy[k] = node.loz[k] = std::numeric_limits<float>::infinity();
+        node.hix[k] = node.hiy[k] = node.hiz[k] = -std::numeric_limits<float>::infinity();
         node.child[k] = kEmptyChild;
         node.reserved[k] = 0;
         continue;

@@ -512,7 +512,9 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
     const float t0z = fmaf(loz[i], inv.z, -oi.z), t1z = fmaf(hiz[i], inv.z, -oi.z);
     const float tn = fmaxf(fmaxf(t0x, t0y), fmaxf(t0z, 0.0f));
     const float tf = fminf(fminf(t1x, t1y), fminf(t1z, tmax));
-    const bool hit = child[i] != kEmptyChild && tn <= tf * 1.0000005f;
+    // empty slots hold an inverted box (lo = +inf, hi = -inf), which every
+    // slab test misses: no separate check of the child entry
+    const bool hit = tn <= tf * 1.0000005f;
     key[i] = hit ? tn : kInfF;
     ent[i] = child[i];
   }

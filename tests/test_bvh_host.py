@@ -93,6 +93,12 @@ def test_leaves_and_records_are_consistent(built):
     lo, hi, held = leaf_boxes(built["nodes"], n)
     assert np.all(held == 1)  # every record sits in exactly one leaf
     assert np.all(built["nodes"]["reserved"] == 0)
+    # empty slots hold inverted boxes, which every slab test misses
+    empty = built["nodes"]["child"] == _lib.EMPTY_CHILD
+    for ax in "xyz":
+        assert np.all(np.isposinf(built["nodes"]["lo_" + ax][empty]))
+        assert np.all(np.isneginf(built["nodes"]["hi_" + ax][empty]))
+        assert np.all(built["nodes"]["lo_" + ax][~empty] <= built["nodes"]["hi_" + ax][~empty])
     inner = built["nodes"]["child"][built["nodes"]["child"] >= 0]
     assert inner.min() >= 1 and inner.max() < info["n_nodes"]
     assert len(np.unique(inner)) == len(inner) == info["n_nodes"] - 1  # a tree
