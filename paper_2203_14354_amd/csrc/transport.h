@@ -525,24 +525,28 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   cswap(key[2], ent[2], key[3], ent[3]);
   cswap(key[1], ent[1], key[2], ent[2]);
   cswap(key[0], ent[0], key[1], ent[1]);
-  node = -1;
-  constexpr int32_t kNone = -1 - 0x7fffffff;
+  constexpr int32_t kNone = -1 - 0x7fffffff;  // no entry (leaf entries stay above it)
+  // the held leaf and the followed node as stack entries, so that a spill is
+  // the entry itself (no conversions per child)
+  int32_t held_leaf = leaf >= 0 ? ~leaf : kNone;
+  int32_t next_node = kNone;
   st.reserve4();
   int32_t npush = 0;
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     const int32_t e = ent[i];
     const bool hit = key[i] != kInfF;
-    // the nearer leaf keeps the leaf slot, the nearer inner node is followed;
+    // the later leaf keeps the leaf slot, the later inner node is followed;
     // the previous holder spills (selects only: branches here cost more)
     const bool is_leaf = e < 0;
-    const int32_t held = is_leaf ? (leaf >= 0 ? ~leaf : kNone) : (node >= 0 ? node : kNone);
-    const int32_t spill = hit ? held : kNone;
-    leaf = hit && is_leaf ? ~e : leaf;
-    node = hit && !is_leaf ? e : node;
+    const int32_t spill = hit ? (is_leaf ? held_leaf : next_node) : kNone;
+    held_leaf = hit && is_leaf ? e : held_leaf;
+    next_node = hit && !is_leaf ? e : next_node;
     st.put(npush, spill);  // a slot above the top: harmless when nothing spills
     npush += spill != kNone ? 1 : 0;
   }
+  node = max(next_node, -1);
+  leaf = held_leaf != kNone ? ~held_leaf : -1;
   if (st.sp + npush > st.total) return false;
   st.sp += npush;
   return true;
