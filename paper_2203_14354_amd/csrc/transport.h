@@ -367,12 +367,16 @@ __device__ __forceinline__ float intersect(const RayW& r, const float* va, const
   const float u = __fsub_rn(__fmul_rn(cx, by), __fmul_rn(cy, bx));
   const float v = __fsub_rn(__fmul_rn(ax, cy), __fmul_rn(ay, cx));
   const float w = __fsub_rn(__fmul_rn(bx, ay), __fmul_rn(by, ax));
-  if ((u < 0.0f || v < 0.0f || w < 0.0f) && (u > 0.0f || v > 0.0f || w > 0.0f)) return kInfF;
+  // mixed edge signs: outside.  Written without branches: the wave runs the
+  // test for every lane anyway, and the exec-mask branches cost more than the
+  // distance computed for lanes that then discard it.
+  const bool neg = (u < 0.0f) | (v < 0.0f) | (w < 0.0f);
+  const bool pos = (u > 0.0f) | (v > 0.0f) | (w > 0.0f);
   const float det = __fadd_rn(__fadd_rn(u, v), w);
-  if (det == 0.0f) return kInfF;
   const float az = r.sz * akz, bz = r.sz * bkz, cz = r.sz * ckz;
   const float t = __fadd_rn(__fadd_rn(__fmul_rn(u, az), __fmul_rn(v, bz)), __fmul_rn(w, cz));
-  return t * __builtin_amdgcn_rcpf(det);  // hardware reciprocal, 1 ulp
+  const bool inside = !(neg & pos) & (det != 0.0f);
+  return inside ? t * __builtin_amdgcn_rcpf(det) : kInfF;  // hardware reciprocal, 1 ulp
 }
 
 struct Best {
@@ -390,14 +394,14 @@ __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, i
   const int32_t id = __float_as_int(A.w);
   const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
   const float t = intersect(r, va, vb, vc);
-  // the skipped triangle is rejected only here: an early return on its id
-  // lets the compiler load the id alone first, a second memory round trip
-  if (id == skip || !(t > tmin) || !(t <= b.t) || !(t < kInfF)) return;
-  if (t < b.t || b.tri < 0 || id < b.tri) {
-    b.t = t;
-    b.tri = id;
-    b.rec = k;
-  }
+  // the skipped triangle is rejected only here (an early return on its id
+  // lets the compiler load the id alone first, a second memory round trip);
+  // selects instead of branches: ties in t go to the lower triangle index
+  const bool hit = (id != skip) & (t > tmin) & (t <= b.t) & (t < kInfF);
+  const bool take = hit & ((t < b.t) | (b.tri < 0) | (id < b.tri));
+  b.t = take ? t : b.t;
+  b.tri = take ? id : b.tri;
+  b.rec = take ? k : b.rec;
 }
 
 struct Counters {
@@ -1118,10 +1122,10 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
       }
       if (leaf >= 0) {
         // one triangle per micro-step: the packed leaf advances to its next triangle
-        const int32_t k = leaf >> 3, rest = leaf & 7;
         if (kCount) cnt.tris++;
-        test_triangle(a.tris, k, ray, a.eps, p.last_tri, b);
-        leaf = rest > 0 ? (((k + 1) << 3) | (rest - 1)) : -1;
+        test_triangle(a.tris, leaf >> 3, ray, a.eps, p.last_tri, b);
+        // next triangle of the leaf: first + 1, count - 1 (leaf + 7), or done
+        leaf = (leaf & 7) != 0 ? leaf + 7 : -1;
       }
       if (leaf < 0 && node < 0 && stack.sp > 0) {
         const int32_t e = stack.pop();
