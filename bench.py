@@ -99,7 +99,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the transport has no multi-GPU path in this build", file=sys.stderr)
+              "the transport library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch

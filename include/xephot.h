@@ -43,7 +43,7 @@ typedef enum xp_status {
   XP_ERR_MESH = -3,        /* mesh failed validation */
   XP_ERR_HIP = -4,         /* a HIP runtime call failed */
   XP_ERR_OOM = -5,         /* device or host allocation failed */
-  XP_ERR_UNSUPPORTED = -6  /* valid request this build cannot serve (e.g. BVH too deep) */
+  XP_ERR_UNSUPPORTED = -6  /* valid request the library cannot serve (e.g. BVH too deep) */
 } xp_status;
 
 /* Terminal flags of a photon (low byte) plus the GEOMETRY_ERROR bit. */
