@@ -320,13 +320,15 @@ typedef struct xp_launch_cfg {
                               closest-hit searches to run the interactions, tallies and
                               refills once at least this many of its 64 lanes are not
                               searching, 1..64 (0 = default 32) */
-  int32_t block_tally;     /* hit-map and gradient tallies of a launch without records
-                              or counters: 1 = summed per workgroup in LDS and added to
-                              device memory once per workgroup, when they fit without
-                              lowering the occupancy; -1 = atomics to device memory per
-                              detected photon; 0 = default (LDS for at most 64 cells).
-                              Hit maps are identical either way; gradients differ only
-                              in summation order */
+  int32_t block_tally;     /* tallies of a launch without records or counters, summed
+                              per workgroup in LDS and added to device memory once per
+                              workgroup (when they fit without lowering the occupancy)
+                              instead of one device-memory atomic per photon: 1 = the hit
+                              map and gradients at any size that fits; 0 = default (hit
+                              map and gradients for at most 64 cells); with 0 or 1 the
+                              loss table (up to 4 KB) and the arrival-time histogram (up
+                              to 8 KB) too; -1 = none.  Integer tallies are identical
+                              either way; gradients differ only in summation order */
 } xp_launch_cfg;
 
 /* One per photon (indexed by the launch-local photon index), written when
