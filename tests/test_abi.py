@@ -55,6 +55,51 @@ def test_struct_layouts_match_header():
     assert _lib.RECORD_DTYPE.itemsize == 96
 
 
+_C_STRUCTS = {"Material": "xp_material", "Surface": "xp_surface", "BvhOptions": "xp_bvh_options",
+              "BvhInfo": "xp_bvh_info", "Sources": "xp_sources", "ExtraTallies": "xp_extra_tallies",
+              "RunParams": "xp_run_params", "LaunchCfg": "xp_launch_cfg"}
+
+
+def test_struct_offsets_match_header(tmp_path):
+    """Every field of the ctypes mirrors (and of the photon-record dtype) has
+    the offset and size the C compiler gives the header's struct member, and
+    every struct has the header's size: a C program built against
+    include/xephot.h prints them."""
+    from paper_2203_14354_amd import _lib
+    mirrors = {c: [(f, getattr(getattr(_lib, k), f).offset, getattr(getattr(_lib, k), f).size)
+                   for f, _ in getattr(_lib, k)._fields_]
+               for k, c in _C_STRUCTS.items()}
+    mirrors["xp_photon_record"] = [(f, _lib.RECORD_DTYPE.fields[f][1],
+                                    _lib.RECORD_DTYPE.fields[f][0].itemsize)
+                                   for f in _lib.RECORD_DTYPE.names]
+    sizes = {c: ctypes.sizeof(getattr(_lib, k)) for k, c in _C_STRUCTS.items()}
+    sizes["xp_photon_record"] = _lib.RECORD_DTYPE.itemsize
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "xephot.h"',
+             'int main(void) {']
+    for c, fields in mirrors.items():
+        lines.append(f'  printf("{c} sizeof %zu\\n", sizeof({c}));')
+        for f, _, _ in fields:
+            lines.append(f'  printf("{c} {f} %zu %zu\\n", offsetof({c}, {f}), '
+                         f'sizeof((({c} *)0)->{f}));')
+    lines += ['  return 0;', '}']
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        parts = line.split()
+        if parts[1] == "sizeof":
+            got[(parts[0], None)] = int(parts[2])
+        else:
+            got[(parts[0], parts[1])] = (int(parts[2]), int(parts[3]))
+    for c, fields in mirrors.items():
+        assert got[(c, None)] == sizes[c], c
+        for f, off, size in fields:
+            assert got[(c, f)] == (off, size), (c, f)
+
+
 def test_argument_validation_without_device(lib):
     from paper_2203_14354_amd import _lib
     assert lib.xp_version().startswith(b"xephot")
