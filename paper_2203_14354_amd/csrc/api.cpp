@@ -15,10 +15,6 @@
 
 #include "xp_internal.h"
 
-namespace xp {
-
-}
-
 struct xp_context {
   int device = 0;
   int n_cu = 0;
