@@ -45,18 +45,26 @@ constexpr float kCns = 0.299792458f;  // m/ns
 // ---------------------------------------------------------------------------
 struct R4 { float u0, u1, u2, u3; };
 
+// The key (the seed) must be the same in every lane of the wave: it is held in
+// scalar registers.  The empty asm makes the compiler derive the round keys
+// per call on the scalar unit instead of keeping all twenty live through the
+// transport loop, where they crowd out other scalar values.
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r > 0) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    // one 32 x 32 -> 64-bit multiply-add instruction per product
+    // one 32 x 32 -> 64-bit multiply-add instruction per product, and one
+    // three-input bitwise instruction (truth table 0x96: a ^ b ^ c) per
+    // new word
     const uint64_t p0 = uint64_t(c0) * 0xD2511F53ull;
     const uint64_t p1 = uint64_t(c2) * 0xCD9E8D57ull;
-    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(p0 >> 32), c3, k1, 0x96);
     c0 = n0;
     c1 = uint32_t(p1);
     c2 = n2;
