@@ -154,6 +154,13 @@ def main():
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "search_lane_utilization": (st[13] / st[12]) if st[12] else None,
                 "kernel": "propagate_kernel<forward>", "avg_launch_s": kern_s}
+    if achieved > HBM_PEAK:
+        # the declared roof is HBM, but the search's nodes and triangle records
+        # (about 100 MB) are read from L2 and the Infinity Cache: `traffic` is
+        # what actually passes L2, and the SQ counters show VALU issue binding
+        roofline["note"] = ("algorithmic bytes per second above the HBM peak: the BVH and "
+                            "triangle records are served by L2 and the Infinity Cache; "
+                            "the kernel is bound by VALU issue")
 
     extras = {}
     if not args.no_extras:

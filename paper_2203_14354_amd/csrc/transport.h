@@ -95,7 +95,14 @@ __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-__device__ __forceinline__ f3 normalize(f3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
+// Hardware square root and reciprocal (about 1 ulp).  The compiler wraps
+// sqrtf and 1/x in range scaling for denormal arguments (five or six
+// instructions instead of one); the arguments below are normal numbers or
+// zero, where the bare instruction gives the same result.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_div(float a, float b) { return a * hw_rcp(b); }
+__device__ __forceinline__ f3 normalize(f3 a) { return hw_rcp(hw_sqrt(dot(a, a))) * a; }
 __device__ __forceinline__ bool finite3(f3 a) {
   return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
 }
@@ -106,7 +113,7 @@ __device__ __forceinline__ float comp(f3 a, int k) { return k == 0 ? a.x : (k ==
 // of n_z is rounding noise and must not select the basis
 __device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
   const float s = n.z >= -0.5f ? 1.0f : -1.0f;
-  const float a = -1.0f / (s + n.z);
+  const float a = -hw_rcp(s + n.z);
   const float b = n.x * n.y * a;
   b1 = {1.0f + s * n.x * n.x * a, s * b, -s * n.x};
   b2 = {b, s + n.y * n.y * a, -n.y};
@@ -114,7 +121,7 @@ __device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
 
 __device__ __forceinline__ f3 isotropic(float u0, float u1) {
   const float c = 1.0f - 2.0f * u0;
-  const float s = sqrtf(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
+  const float s = hw_sqrt(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
   float sp, cp;
   sincospif(2.0f * u1, &sp, &cp);
   return {s * cp, s * sp, c};
@@ -166,8 +173,8 @@ __device__ __forceinline__ void rayleigh(Photon& p, uint32_t s0, uint32_t s1, ui
 __device__ __forceinline__ void lambertian(Photon& p, f3 n_out, const R4& r) {
   f3 b1, b2;
   onb(n_out, b1, b2);
-  const float ct = sqrtf(r.u0);
-  const float st = sqrtf(fmaxf(0.0f, 1.0f - r.u0));
+  const float ct = hw_sqrt(r.u0);
+  const float st = hw_sqrt(fmaxf(0.0f, 1.0f - r.u0));
   float sp, cp;
   sincospif(2.0f * r.u1, &sp, &cp);
   p.dir = normalize((st * cp) * b1 + (st * sp) * b2 + ct * n_out);
@@ -185,20 +192,21 @@ __device__ __forceinline__ void specular(Photon& p, f3 n) {
 __device__ __forceinline__ bool fresnel(Photon& p, f3 nhat, float n1, float n2, float u) {
   const f3 d = p.dir, e = p.pol;
   const float ci = -dot(d, nhat);
-  const float eta = n1 / n2;
+  const float eta = hw_div(n1, n2);
   const float st2 = eta * eta * (1.0f - ci * ci);
   if (st2 >= 1.0f) {
     specular(p, nhat);
     return false;
   }
-  const float ct = sqrtf(1.0f - st2);
-  const float rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
-  const float rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
-  const float ts = 2.0f * n1 * ci / (n1 * ci + n2 * ct);
-  const float tp = 2.0f * n1 * ci / (n2 * ci + n1 * ct);
+  // 1 - st2 >= 2^-24 here, and the denominators are positive
+  const float ct = hw_sqrt(1.0f - st2);
+  const float rs = hw_div(n1 * ci - n2 * ct, n1 * ci + n2 * ct);
+  const float rp = hw_div(n2 * ci - n1 * ct, n2 * ci + n1 * ct);
+  const float ts = hw_div(2.0f * n1 * ci, n1 * ci + n2 * ct);
+  const float tp = hw_div(2.0f * n1 * ci, n2 * ci + n1 * ct);
   const f3 sv = cross(d, nhat);
-  const float sl = sqrtf(dot(sv, sv));
-  const f3 s = (sl < 1e-6f) ? e : (1.0f / sl) * sv;
+  const float sl = hw_sqrt(dot(sv, sv));
+  const f3 s = (sl < 1e-6f) ? e : hw_rcp(sl) * sv;
   const float as = dot(e, s);
   const float ap = dot(e, cross(s, d));
   const float R = as * as * rs * rs + ap * ap * rp * rp;
@@ -233,14 +241,14 @@ __device__ __forceinline__ DevMaterial material_at(const LaunchArgs& a, int32_t 
     } else {
       int32_t i = 0;
       while (t.lambda[i + 1] < lam) ++i;
-      const float w = (lam - t.lambda[i]) / (t.lambda[i + 1] - t.lambda[i]);
+      const float w = hw_div(lam - t.lambda[i], t.lambda[i + 1] - t.lambda[i]);
       n = t.index[i] + w * (t.index[i + 1] - t.index[i]);
       ia = t.inv_abs[i] + w * (t.inv_abs[i + 1] - t.inv_abs[i]);
       ir = t.inv_ray[i] + w * (t.inv_ray[i + 1] - t.inv_ray[i]);
     }
     r.n = n;
-    r.abs_len = ia > 0.0f ? 1.0f / ia : kInfF;
-    r.ray_len = ir > 0.0f ? 1.0f / ir : kInfF;
+    r.abs_len = ia > 0.0f ? hw_rcp(ia) : kInfF;
+    r.ray_len = ir > 0.0f ? hw_rcp(ir) : kInfF;
   }
   return r;
 }
@@ -353,9 +361,9 @@ __device__ __forceinline__ RayW make_ray(f3 o, f3 d, int32_t n_tris) {
   const int ky = kx == 2 ? 0 : kx + 1;
   r.o = f3{comp(o, kx), comp(o, ky), comp(o, kz)};
   const float dz = comp(d, kz);
-  r.sx = comp(d, kx) / dz;
-  r.sy = comp(d, ky) / dz;
-  r.sz = 1.0f / dz;
+  r.sx = hw_div(comp(d, kx), dz);
+  r.sy = hw_div(comp(d, ky), dz);
+  r.sz = hw_rcp(dz);
   r.toff = kx * n_tris;  // (kz + 1) mod 3 == kx
   return r;
 }
@@ -582,9 +590,9 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
                                          int32_t skip, Best& b, Counters& cnt) {
   const RayW ray = make_ray(o, d, n_tris);
   const float tiny = 1e-30f;
-  const f3 inv{1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
-               1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
-               1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z))};
+  const f3 inv{hw_rcp(fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
+               hw_rcp(fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
+               hw_rcp(fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z))};
   const f3 oi{o.x * inv.x, o.y * inv.y, o.z * inv.z};
   int32_t node = 0;   // inner node to visit next, or -1
   int32_t leaf = -1;  // postponed leaf (packed), or -1
@@ -695,7 +703,7 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
     p.event = a.per_source_events ? int32_t(s) : 0;
   } else {
     const R4 q = draw(a.seed_lo, a.seed_hi, pid, 0u, 1u);
-    const float rr = a.cyl_r * sqrtf(q.u0);
+    const float rr = a.cyl_r * hw_sqrt(q.u0);
     float sp, cp;
     sincospif(2.0f * q.u1, &sp, &cp);
     p.pos = {rr * cp, rr * sp, a.cyl_zlo + (a.cyl_zhi - a.cyl_zlo) * q.u2};
@@ -757,7 +765,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
       return true;
     }
     p.pos = p.pos + d_bulk * p.dir;
-    p.time += d_bulk * m.n / kCns;
+    p.time += hw_div(d_bulk * m.n, kCns);
     if (kGradAcc && in_grad) p.path_len += d_bulk;
     if (d_abs <= d_sca) {
       p.flag |= F_BULK_ABSORB;
@@ -769,7 +777,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
   } else {
     const int32_t k = b.tri;
     p.pos = p.pos + b.t * p.dir;
-    p.time += b.t * m.n / kCns;
+    p.time += hw_div(b.t * m.n, kCns);
     if (kGradAcc && in_grad) p.path_len += b.t;
     const float4 A = *reinterpret_cast<const float4*>(a.tris[b.rec].a);
     const float4 B = *reinterpret_cast<const float4*>(a.tris[b.rec].b);
@@ -1094,9 +1102,9 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         b = Best{fminf(sd.d_abs, sd.d_sca), -1, -1};
         ray = make_ray(p.pos, p.dir, a.n_tris);
         const float tiny = 1e-30f;
-        inv = f3{1.0f / (fabsf(p.dir.x) > tiny ? p.dir.x : copysignf(tiny, p.dir.x)),
-                 1.0f / (fabsf(p.dir.y) > tiny ? p.dir.y : copysignf(tiny, p.dir.y)),
-                 1.0f / (fabsf(p.dir.z) > tiny ? p.dir.z : copysignf(tiny, p.dir.z))};
+        inv = f3{hw_rcp(fabsf(p.dir.x) > tiny ? p.dir.x : copysignf(tiny, p.dir.x)),
+                 hw_rcp(fabsf(p.dir.y) > tiny ? p.dir.y : copysignf(tiny, p.dir.y)),
+                 hw_rcp(fabsf(p.dir.z) > tiny ? p.dir.z : copysignf(tiny, p.dir.z))};
         oi = f3{p.pos.x * inv.x, p.pos.y * inv.y, p.pos.z * inv.z};
         node = 0;
         leaf = -1;
