@@ -119,11 +119,20 @@ __device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
   b2 = {b, s + n.y * n.y * a, -n.y};
 }
 
+// sin(2 pi u) and cos(2 pi u) by the hardware instructions, which take their
+// argument in revolutions: one instruction each instead of the library's
+// range reduction and polynomials, with a maximal absolute error of 2.7e-7
+// over the uniforms u01 produces (the library's sincospif: 2.0e-7)
+__device__ __forceinline__ void sincos_rev(float u, float& s, float& c) {
+  s = __builtin_amdgcn_sinf(u);
+  c = __builtin_amdgcn_cosf(u);
+}
+
 __device__ __forceinline__ f3 isotropic(float u0, float u1) {
   const float c = 1.0f - 2.0f * u0;
   const float s = hw_sqrt(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
   float sp, cp;
-  sincospif(2.0f * u1, &sp, &cp);
+  sincos_rev(u1, sp, cp);
   return {s * cp, s * sp, c};
 }
 
@@ -131,7 +140,7 @@ __device__ __forceinline__ f3 random_polarization(f3 d, float u) {
   f3 b1, b2;
   onb(d, b1, b2);
   float sp, cp;
-  sincospif(2.0f * u, &sp, &cp);
+  sincos_rev(u, sp, cp);
   return cp * b1 + sp * b2;
 }
 
@@ -176,7 +185,7 @@ __device__ __forceinline__ void lambertian(Photon& p, f3 n_out, const R4& r) {
   const float ct = hw_sqrt(r.u0);
   const float st = hw_sqrt(fmaxf(0.0f, 1.0f - r.u0));
   float sp, cp;
-  sincospif(2.0f * r.u1, &sp, &cp);
+  sincos_rev(r.u1, sp, cp);
   p.dir = normalize((st * cp) * b1 + (st * sp) * b2 + ct * n_out);
   p.pol = random_polarization(p.dir, r.u2);
 }
@@ -705,7 +714,7 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
     const R4 q = draw(a.seed_lo, a.seed_hi, pid, 0u, 1u);
     const float rr = a.cyl_r * hw_sqrt(q.u0);
     float sp, cp;
-    sincospif(2.0f * q.u1, &sp, &cp);
+    sincos_rev(q.u1, sp, cp);
     p.pos = {rr * cp, rr * sp, a.cyl_zlo + (a.cyl_zhi - a.cyl_zlo) * q.u2};
   }
 }
