@@ -7,7 +7,10 @@ Philox stream per photon):
   * integer hit counts identical on the photons that agree, and the hit map
     identical to the histogram of the GPU's own photon records;
   * per-sensor hit-count chi^2/ndf < 1.2 against the oracle;
-  * samplers elementwise within 1e-5 (FP32 rounding of the same formulas);
+  * samplers elementwise within 1e-6 (directions, positions in m) and 5e-6
+    (polarizations, renormalised after a projection that can be short): FP32
+    rounding of the same formulas, with the hardware square root, reciprocal,
+    sine and cosine (measured at most 2.4e-7 and 1.5e-6);
   * closest hit: BVH traversal bitwise equal to brute force on the GPU.
 """
 import math
@@ -61,12 +64,12 @@ def test_samplers_match_oracle(rt, kind):
     od, oe = oracle.sample(kind, 11, 123, n, in_dir=nrm.astype(np.float32).astype(np.float64),
                            in_pol=pol.astype(np.float32).astype(np.float64), cyl=cyl)
     dd = np.abs(d.cpu().numpy() - od).max(axis=1)
-    ok = dd < 1e-5
+    ok = dd < 1e-6
     if kind == 3:
         assert ok.all()
         return
     de = np.abs(e.cpu().numpy() - oe).max(axis=1)
-    ok &= de < 1e-4
+    ok &= de < 5e-6
     # Rayleigh acceptance may flip where u equals the threshold to FP32 rounding
     assert ok.mean() >= (0.9999 if kind == 2 else 1.0)
 
