@@ -52,8 +52,11 @@ def build(verbose: bool = False) -> str:
     # -fno-hip-fp32-correctly-rounded-divide-sqrt: FP32 division and square root
     # by the hardware reciprocal/root instructions (a few ulp) instead of the
     # multi-instruction correctly rounded sequences
+    # -fgpu-flush-denormals-to-zero: FP32 denormals flush to zero, so the library
+    # math left on the path (logarithms, rare-branch divisions) needs no range
+    # scaling for them; no value on the transport path is that small
     dev = ["-x", "hip", f"--offload-arch={ARCH}", "-munsafe-fp-atomics", "-ffp-contract=on",
-           "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+           "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     srcs = HOST_SOURCES + DEVICE_SOURCES
     objs = [os.path.join(BUILD_DIR, s + ".o") for s in srcs]
