@@ -206,7 +206,7 @@ class Detector:
         if th is not None or lt is not None:
             extra = ExtraTallies(d_time_hist=_ptr(th), n_time_bins=th.shape[-1] if th is not None else 0,
                                  time_bin_ns=float(time_bin_ns), d_loss=_ptr(lt))
-        lc = LaunchCfg(**launch) if launch else None
+        lc = launch_cfg(launch)
         s = stream if stream is not None else current_stream(dev)
         sstruct = ds.struct(n)
         rp = self.run_params(seed, pid_base, max_steps, eps, grad_material)
@@ -227,7 +227,7 @@ class Detector:
             raise ValueError("grad_hits must have n_events * n_channels elements")
         gp = grad_params if grad_params is not None else torch.zeros(4, dtype=torch.float64,
                                                                      device=self.device)
-        lc = LaunchCfg(**launch) if launch else None
+        lc = launch_cfg(launch)
         s = stream if stream is not None else current_stream(self.device)
         sstruct = ds.struct()
         rp = self.run_params(seed, pid_base, max_steps, eps, grad_material)
@@ -261,6 +261,16 @@ class Detector:
                                       float(tmax), 1 if brute else 0, _ptr(tri), _ptr(t),
                                       ctypes.c_void_p(s)), self.ctx)
         return tri, t
+
+
+def launch_cfg(launch: Optional[dict]):
+    """The xp_launch_cfg of a launch-configuration dict, or None for the
+    context's configuration.  Fields the dict leaves out take the library's
+    defaults: 0 for every field but lds_levels, whose default is -1 (0 would
+    stage no BVH levels in LDS)."""
+    if not launch:
+        return None
+    return LaunchCfg(**{"lds_levels": -1, **launch})
 
 
 def bvh_build_host(vertices, triangles, max_leaf_size=1, sah_bins=32, split_budget=0.0):

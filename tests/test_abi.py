@@ -186,3 +186,13 @@ def test_safety_grid_bounds_are_lower_bounds(lib, which):
         best = np.minimum(best, _point_triangle_distance(pts, vv[tri[0]], vv[tri[1]], vv[tri[2]]))
     assert np.all(bound <= best), (bound - best).max()
     assert np.mean(bound > 0) > 0.3  # and the bounds are not vacuous
+
+
+def test_launch_dict_defaults():
+    """A launch dict that leaves a field out gets the library default for it:
+    lds_levels -1 (the default), not 0 (no staged levels)."""
+    from paper_2203_14354_amd.runtime import launch_cfg
+    assert launch_cfg(None) is None and launch_cfg({}) is None
+    lc = launch_cfg({"wave_batch": 24})
+    assert (lc.wave_batch, lc.lds_levels, lc.block_size, lc.stack_lds) == (24, -1, 0, 0)
+    assert launch_cfg({"lds_levels": 0}).lds_levels == 0
