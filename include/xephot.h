@@ -312,7 +312,9 @@ typedef struct xp_launch_cfg {
   int32_t block_size;      /* threads per workgroup: 64, 128 or 256 (0 = default) */
   int32_t blocks_per_cu;   /* resident workgroups per CU (0 = as many as fit) */
   int32_t chunk;           /* photon ids claimed per wave refill (0 = default 64) */
-  int32_t lds_levels;      /* BVH levels staged in LDS, 0..4 (-1 = default) */
+  int32_t lds_levels;      /* BVH levels staged in LDS, 0..4; -1 = automatic: four,
+                              or three where the fourth would lower the occupancy or
+                              leave the launch's LDS tallies (block_tally) no room */
   int32_t stack_lds;       /* traversal-stack entries per lane kept in LDS, a power of
                               two in 4..64 (0 = default 16); deeper entries spill to a
                               global overflow area allocated by xp_build_bvh */

@@ -112,7 +112,7 @@ int upload_channel_map(xp_context* ctx) {
 }
 
 xp_launch_cfg default_cfg() {
-  return xp_launch_cfg{256, 0, 64, 3, xp::kStackLds, xp::kWaveBatch, 0};
+  return xp_launch_cfg{256, 0, 64, -1, xp::kStackLds, xp::kWaveBatch, 0};
 }
 
 // Validates (ctx, src, rp) for a launch and fills the kernel arguments.
@@ -178,7 +178,12 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   lc = lc_in ? *lc_in : (ctx->tuned ? ctx->tuned_cfg : default_cfg());
   if (lc.block_size == 0) lc.block_size = 256;
   if (lc.chunk <= 0) lc.chunk = 64;
-  if (lc.lds_levels < 0) lc.lds_levels = 3;
+  // lds_levels < 0: automatic (four staged levels, three where the fourth
+  // would lower the occupancy or leave the launch's LDS tallies no room); the
+  // resolved configuration keeps -1 so that choose_block_tally may still drop
+  // the fourth level
+  const bool auto_levels = lc.lds_levels < 0;
+  if (auto_levels) lc.lds_levels = -1;
   if (lc.stack_lds == 0) lc.stack_lds = xp::kStackLds;
   if (lc.wave_batch == 0) lc.wave_batch = xp::kWaveBatch;
   if (lc.wave_batch < 1 || lc.wave_batch > 64)
@@ -197,7 +202,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.tris = ctx->d_tris;
   a.n_tris = int32_t(ctx->stats.n_references);
   a.channel_of_sensor = ctx->d_channel;
-  const int levels = std::min<int>(lc.lds_levels, int(ctx->bvh.level_end.size()));
+  const int levels = std::min<int>(auto_levels ? 4 : lc.lds_levels, int(ctx->bvh.level_end.size()));
   a.n_lds_nodes = levels > 0 ? ctx->bvh.level_end[levels - 1] : 0;
   a.stack_lds = lc.stack_lds;
   a.stack_total = ctx->bvh.max_stack;
@@ -275,14 +280,28 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     a.surfs[i].film_n = s.film_n;
     a.surfs[i].two_pi_d = float(2.0 * 3.14159265358979323846 * double(s.film_thickness_nm));
   }
-  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size, 0);
+  size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, lc.block_size, 0);
+  int per_cu = 0;
+  hipError_t e = hipSuccess;
+  if (lds <= ctx->max_lds) e = xp::max_blocks_per_cu(lc.block_size, lds, false, false, &per_cu);
+  if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+  if (auto_levels && levels > 3) {
+    // the fourth level only where it costs no occupancy
+    const int32_t n3 = ctx->bvh.level_end[2];
+    const size_t lds3 = xp::propagate_lds_bytes(n3, a.stack_lds, lc.block_size, 0);
+    int per_cu3 = 0;
+    if (lds3 <= ctx->max_lds) e = xp::max_blocks_per_cu(lc.block_size, lds3, false, false, &per_cu3);
+    if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    if (lds > ctx->max_lds || per_cu3 > per_cu) {
+      a.n_lds_nodes = n3;
+      lds = lds3;
+      per_cu = per_cu3;
+    }
+  }
   if (lds > ctx->max_lds)
     return fail(ctx, XP_ERR_UNSUPPORTED, "LDS request of " + std::to_string(lds) +
                                              " bytes exceeds the device limit; use fewer lds_levels "
                                              "or a smaller block");
-  int per_cu = 0;
-  const hipError_t e = xp::max_blocks_per_cu(lc.block_size, lds, false, false, &per_cu);
-  if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
   if (per_cu <= 0) return fail(ctx, XP_ERR_UNSUPPORTED, "kernel does not fit on a CU");
   if (lc.blocks_per_cu <= 0 || lc.blocks_per_cu > per_cu) lc.blocks_per_cu = per_cu;
   grid = ctx->n_cu * lc.blocks_per_cu;
@@ -336,11 +355,21 @@ void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_l
     }
   }
   if (bytes == 0) return;
-  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, cfg.block_size, bytes);
-  int per_cu = 0;
-  if (lds <= ctx->max_lds &&
-      xp::max_blocks_per_cu(cfg.block_size, lds, false, true, &per_cu) == hipSuccess &&
-      per_cu >= cfg.blocks_per_cu) {
+  auto fits = [&](int32_t n_nodes) {
+    const size_t lds = xp::propagate_lds_bytes(n_nodes, a.stack_lds, cfg.block_size, bytes);
+    int per_cu = 0;
+    return lds <= ctx->max_lds &&
+           xp::max_blocks_per_cu(cfg.block_size, lds, false, true, &per_cu) == hipSuccess &&
+           per_cu >= cfg.blocks_per_cu;
+  };
+  if (fits(a.n_lds_nodes)) {
+    a.tally_bytes = int32_t(bytes);
+    return;
+  }
+  // automatic levels: the tallies take the fourth staged level's LDS
+  if (cfg.lds_levels < 0 && ctx->bvh.level_end.size() >= 4 &&
+      a.n_lds_nodes > ctx->bvh.level_end[2] && fits(ctx->bvh.level_end[2])) {
+    a.n_lds_nodes = ctx->bvh.level_end[2];
     a.tally_bytes = int32_t(bytes);
     return;
   }
@@ -946,7 +975,7 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     int rc = XP_OK;
     std::vector<xp_launch_cfg> cands;
     for (int b : {64, 256})
-      for (int l : {0, 3})
+      for (int l : {0, -1})
         for (int sl : {8, 16})
           for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb, 0});
     // then the fastest of these with the block tallies forced on (the default
