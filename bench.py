@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--cache-probe", action="store_true",
                     help="only measure streaming-read bandwidth from buffers resident in the L2 "
                          "caches (16 MB), the Infinity Cache (64-192 MB) and HBM (8 GB)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only measure the VALU issue rate of kernels of known instruction count "
+                         "(FP32 multiply-add, FP32 reciprocal, integer xor-add)")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="BYTES",
                     help="also run one device-to-device copy of BYTES bytes (a known-traffic "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -110,6 +113,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.cache_probe:
         print(json.dumps(cache_probe(torch, dev)), flush=True)
+        return
+    if args.valu_probe:
+        print(json.dumps(valu_probe(torch, dev)), flush=True)
         return
     if args.calibration_copy > 0:
         a = torch.ones(args.calibration_copy // 4, dtype=torch.float32, device=dev)
@@ -401,20 +407,22 @@ def design_variants(torch, W, Detector, dev, n=20_000_000):
 def cache_probe(torch, dev):
     """Streaming-read bandwidth of buffers that fit the eight 4 MB L2 caches
     (16 MB: each XCD's workgroups touch one eighth), the 256 MB Infinity Cache
-    (64, 128, 192 MB) and only HBM (8 GB): one launch of 2048 x 256 threads
-    reads each buffer repeatedly (about 16 GB per launch); HIP events time 5
-    launches."""
+    (32 to 192 MB) and only HBM (8 GB): one launch reads each buffer
+    repeatedly (about 16 GB per launch), every thread with four loads in
+    flight (the grid shrinks for small buffers so that each thread has four
+    vectors per pass); HIP events time 5 launches."""
     import ctypes
     from paper_2203_14354_amd import _lib
     lib = _lib.load()
-    blocks = 2048
-    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    out = torch.empty(2048 * 256, dtype=torch.float32, device=dev)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     rates = {}
-    for name, mb in (("l2_16MB", 16), ("infinity_cache_64MB", 64), ("infinity_cache_128MB", 128),
-                     ("infinity_cache_192MB", 192), ("hbm_8GB", 8192)):
+    for name, mb in (("l2_16MB", 16), ("infinity_cache_32MB", 32), ("infinity_cache_64MB", 64),
+                     ("infinity_cache_128MB", 128), ("infinity_cache_192MB", 192),
+                     ("hbm_8GB", 8192)):
         x = torch.ones(mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
         n_vec = x.numel() // 4
+        blocks = int(max(256, min(2048, n_vec // (4 * 256))))
         passes = max(1, (16 << 30) // (mb << 20))
         run = lambda: _lib.check(lib.xp_stream_read(ctypes.c_void_p(x.data_ptr()), n_vec, passes,
                                                     blocks, ctypes.c_void_p(out.data_ptr()), stream))
@@ -423,6 +431,38 @@ def cache_probe(torch, dev):
         rates[name] = n_vec * 16 * passes / statistics.median(d) / 1e9
         del x
     return {"stream_read_GBps": rates}
+
+
+# VALU instructions one iteration of the probe loop issues per wave (64
+# steps on eight chains; the integer step is an xor and an add)
+VALU_PROBE_KINDS = {0: ("fp32_fma", 64), 1: ("fp32_rcp", 64), 2: ("int32_xor_add", 128)}
+
+
+def valu_probe(torch, dev, iters=20_000):
+    """VALU issue rate of kernels of known instruction count: eight workgroups
+    of 256 threads per CU (eight waves per SIMD) run `iters` iterations of
+    the probe loop; HIP events time 5 launches.  Reports wave-instructions per
+    second and the SIMD cycles (at the 2.4 GHz peak clock) per wave64
+    instruction."""
+    import ctypes
+    from paper_2203_14354_amd import _lib
+    lib = _lib.load()
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = n_cu * 8
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    res = {"compute_units": n_cu, "blocks": blocks, "iters": iters}
+    for kind, (name, per_iter) in VALU_PROBE_KINDS.items():
+        run = lambda: _lib.check(lib.xp_valu_probe(kind, iters, blocks,
+                                                   ctypes.c_void_p(out.data_ptr()), stream))
+        run()
+        d, _ = timed_launches(run, 5, torch)
+        t = statistics.median(d)
+        instr = blocks * 4 * per_iter * iters  # wave-instructions (4 waves per block)
+        res[name] = {"seconds": t, "wave_instructions": instr,
+                     "wave_instructions_per_s": instr / t,
+                     "cycles_per_instruction_per_simd": n_cu * 4 * t * 2.4e9 / instr}
+    return {"valu_probe": res}
 
 
 def spectrum_cost(torch, W, det, mesh, dev, n=20_000_000):

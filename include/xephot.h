@@ -492,6 +492,16 @@ int xp_surface_reflectance(int32_t model, float n1, float n_re, float n_im, floa
 int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t blocks, float* out,
                    xp_stream stream);
 
+/* VALU issue probe for the roofline (not part of the transport): `blocks`
+ * workgroups of 256 threads each run `iters` iterations of 64 steps of one
+ * kind on eight independent chains (kind 0: one FP32 multiply-add per step,
+ * 1: one FP32 reciprocal, 2: a 32-bit integer xor and an add) and write one
+ * value per thread to out (device float[blocks * 256]).  A kernel of known
+ * instruction count for calibrating the shader-sequencer counters and
+ * measuring the issue rate the chip sustains.  Errors: XP_ERR_INVALID_ARG,
+ * XP_ERR_HIP. */
+int xp_valu_probe(int32_t kind, int32_t iters, int32_t blocks, float* out, xp_stream stream);
+
 /* Host-only (no device needed): build the safety grid of a mesh (host arrays)
  * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,
  * out_lo float[3] the grid origin, *out_cell the cell size; out_values

@@ -5,6 +5,11 @@ computes, loaded with ctypes.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the library itself never
 does.  It shares no code with the HIP path: both receive the same input arrays
 built by ``paper_2203_14354_amd.workloads`` and compute independently.
+
+The same source built with ``-DXEORACLE_FP32`` (``fp32=True`` below) computes
+the transport in single precision: a diagnostic build that tells whether a
+photon on which the HIP path and the FP64 oracle part is one where FP32
+rounding alone changes the outcome.  Results of record are the FP64 build's.
 """
 from __future__ import annotations
 
@@ -18,6 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "xeoracle.cpp")
 _LIB = os.path.join(_HERE, "libxeoracle.so")
+_LIB32 = os.path.join(_HERE, "libxeoracle_fp32.so")
 
 F_DETECT, F_SENSOR_ABSORB, F_SURFACE_ABSORB, F_BULK_ABSORB = 1, 2, 3, 4
 F_ESCAPED, F_MAX_STEPS, F_NAN_ABORT, F_GEOMETRY_ERROR = 5, 6, 7, 0x100
@@ -32,26 +38,34 @@ RECORD_DTYPE = np.dtype([
 assert RECORD_DTYPE.itemsize == 32 + 9 * 8 + 5 * 8
 
 
+def _compile(out, defines):
+    tmp = out + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           *defines, "-shared", "-fPIC", "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle (g++, OpenMP, no FMA contraction, portable -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-shared", "-fPIC", "-o", tmp, _SRC]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle (g++, OpenMP, no FMA contraction, portable -O2) and
+    its FP32 diagnostic build."""
+    for out, defines in ((_LIB, []), (_LIB32, ["-DXEORACLE_FP32"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            _compile(out, defines)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(fp32: bool = False):
+    """The FP64 oracle library (fp32=True: its FP32 diagnostic build)."""
+    key = bool(fp32)
+    if key not in _libs:
+        path = _LIB32 if key else _LIB
+        if not os.path.exists(path):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                ctypes.c_double)
         L.oracle_scene_create.restype = P
@@ -66,17 +80,21 @@ def lib():
         L.oracle_philox.argtypes = [P, P, P]
         L.oracle_u01.restype = D
         L.oracle_u01.argtypes = [ctypes.c_uint32]
+        L.oracle_is_fp32.restype = I32
         L.oracle_sample.argtypes = [I32, U64, U64, I64, P, P, D, D, D, P, P]
         L.oracle_boundary.restype = I32
         L.oracle_boundary.argtypes = [I32, P, P, P, D, D, D, P, P]
+        L.oracle_model_boundary.restype = I32
+        L.oracle_model_boundary.argtypes = [I32, P, P, P, D, D, D, D, D, D, D, P, P]
         L.oracle_closest_hit.argtypes = [P, I64, P, P, D, D, P, I32, P, P]
         L.oracle_emission_time.argtypes = [U64, U64, I64, D, D, D, P, P]
         L.oracle_wavelength.argtypes = [U64, U64, I64, D, D, P]
         L.oracle_surface_reflectance.argtypes = [I32, D, D, D, D, D, D, I64, P, P, P]
         L.oracle_material_at.argtypes = [P, I32, I64, P, P]
         L.oracle_max_threads.restype = I32
-        _lib = L
-    return _lib
+        assert L.oracle_is_fp32() == (1 if key else 0)
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -86,9 +104,11 @@ def _p(a: Optional[np.ndarray]):
 class Scene:
     """Oracle copy of a mesh plus its optical tables."""
 
-    def __init__(self, mesh, channel_of_sensor=None, n_channels=None, use_bvh=False):
+    def __init__(self, mesh, channel_of_sensor=None, n_channels=None, use_bvh=False,
+                 fp32=False):
         from paper_2203_14354_amd.workloads import materials_array, surfaces_array
         self.mesh = mesh
+        self.lib = lib(fp32)
         self._keep = []
 
         def keep(a, dt):
@@ -110,7 +130,7 @@ class Scene:
             ch = keep(channel_of_sensor, np.int32)
             nch = int(n_channels if n_channels is not None else ch.max() + 1)
         self.n_channels = nch
-        self.handle = lib().oracle_scene_create(
+        self.handle = self.lib.oracle_scene_create(
             _p(v), len(v), _p(t), len(t), _p(mi), _p(mo), _p(su), _p(se), _p(mats), len(mats),
             _p(sp), _p(stags), _p(sopt), len(sp), _p(ch), mesh.n_sensors, nch,
             1 if use_bvh else 0)
@@ -118,7 +138,7 @@ class Scene:
             tab = getattr(mat, "dispersion", None)
             if tab is not None:
                 tab = keep(np.asarray(tab, dtype=np.float32).reshape(-1, 4).T.copy(), np.float32)
-                lib().oracle_scene_set_dispersion(self.handle, m, tab.shape[1], _p(tab[0]),
+                self.lib.oracle_scene_set_dispersion(self.handle, m, tab.shape[1], _p(tab[0]),
                                                   _p(tab[1]), _p(tab[2]), _p(tab[3]))
 
     def material_at(self, m, lambdas):
@@ -126,12 +146,12 @@ class Scene:
         given wavelengths (nm), from its dispersion table."""
         lam = np.ascontiguousarray(lambdas, dtype=np.float64).reshape(-1)
         out = np.zeros((len(lam), 3))
-        lib().oracle_material_at(self.handle, int(m), len(lam), _p(lam), _p(out))
+        self.lib.oracle_material_at(self.handle, int(m), len(lam), _p(lam), _p(out))
         return out
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
-            _lib.oracle_scene_destroy(self.handle)
+        if getattr(self, "handle", None) and getattr(self, "lib", None) is not None:
+            self.lib.oracle_scene_destroy(self.handle)
             self.handle = None
 
     def closest_hit(self, orig, dirs, tmin=0.0, tmax=np.inf, skip=None, brute=False):
@@ -140,7 +160,7 @@ class Scene:
         sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
         tri = np.empty(len(o), dtype=np.int32)
         t = np.empty(len(o), dtype=np.float64)
-        lib().oracle_closest_hit(self.handle, len(o), _p(o), _p(d), float(tmin), float(tmax),
+        self.lib.oracle_closest_hit(self.handle, len(o), _p(o), _p(d), float(tmin), float(tmax),
                                  _p(sk), 1 if brute else 0, _p(tri), _p(t))
         return tri, t
 
@@ -179,7 +199,7 @@ def run(scene: Scene, sources, seed=0, pid_base=0, max_steps=10_000, eps=0.0, gr
     # the time-profile parameters enter as the FP32 values the library receives
     tp = int(getattr(s, "time_profile", 0))
     f32 = lambda x: float(np.float32(x))
-    lib().oracle_run(scene.handle, s.kind, s.medium, s.n_photons, n_src, _p(pos), _p(offs),
+    scene.lib.oracle_run(scene.handle, s.kind, s.medium, s.n_photons, n_src, _p(pos), _p(offs),
                      int(s.count_per_source), 1 if s.per_source_events else 0, _p(dirs), _p(pols),
                      float(s.cyl_radius), float(s.cyl_zlo), float(s.cyl_zhi), tp,
                      f32(getattr(s, "tau_singlet_ns", 0.0)), f32(getattr(s, "tau_triplet_ns", 0.0)),
@@ -210,7 +230,7 @@ def u01(x: int) -> float:
     return lib().oracle_u01(int(x))
 
 
-def sample(kind, seed, pid0, n, in_dir=None, in_pol=None, cyl=(0.0, 0.0, 0.0)):
+def sample(kind, seed, pid0, n, in_dir=None, in_pol=None, cyl=(0.0, 0.0, 0.0), fp32=False):
     """kind 0 emission, 1 Lambertian about in_dir, 2 Rayleigh from (in_dir, in_pol),
     3 uniform-cylinder positions (returned in the first array)."""
     di = None if in_dir is None else np.ascontiguousarray(
@@ -219,7 +239,7 @@ def sample(kind, seed, pid0, n, in_dir=None, in_pol=None, cyl=(0.0, 0.0, 0.0)):
         np.broadcast_to(np.asarray(in_pol, np.float64), (n, 3)))
     od = np.zeros((n, 3))
     op = np.zeros((n, 3))
-    lib().oracle_sample(int(kind), int(seed), int(pid0), int(n), _p(di), _p(pi), float(cyl[0]),
+    lib(fp32).oracle_sample(int(kind), int(seed), int(pid0), int(n), _p(di), _p(pi), float(cyl[0]),
                         float(cyl[1]), float(cyl[2]), _p(od), _p(op))
     return od, op
 
@@ -311,15 +331,38 @@ def loss_table(records, tri_group, n_groups, n_materials):
     return t
 
 
-def boundary(mode, d, e, n, n1=1.0, n2=1.0, u=0.5):
+def boundary(mode, d, e, n, n1=1.0, n2=1.0, u=0.5, fp32=False):
+    """One boundary event (mode 0 Fresnel between indices n1 -> n2, mode 1
+    specular) of a photon (direction d, polarization e) on a plane of unit
+    normal n (either orientation).  Returns (transmitted, new direction, new
+    polarization)."""
     d = np.ascontiguousarray(d, np.float64)
     e = np.ascontiguousarray(e, np.float64)
     n = np.ascontiguousarray(n, np.float64)
     od, op = np.zeros(3), np.zeros(3)
-    tr = lib().oracle_boundary(int(mode), _p(d), _p(e), _p(n), float(n1), float(n2), float(u),
+    tr = lib(fp32).oracle_boundary(int(mode), _p(d), _p(e), _p(n), float(n1), float(n2), float(u),
                                _p(od), _p(op))
     return bool(tr), od, op
 
 
+def model_boundary(model, d, e, n, n1, n_re, n_im, film_n=0.0, film_d_nm=0.0, lam=174.8, u=0.5,
+                   fp32=False):
+    """One reflection off a complex-index (model 1) or thin-film (model 2)
+    surface: returns (reflected, new direction, new polarization); a photon
+    that is not reflected keeps its direction and polarization."""
+    d = np.ascontiguousarray(d, np.float64)
+    e = np.ascontiguousarray(e, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    od, op = d.copy(), e.copy()
+    r = lib(fp32).oracle_model_boundary(int(model), _p(d), _p(e), _p(n), float(n1), float(n_re),
+                                        float(n_im), float(film_n), float(film_d_nm), float(lam),
+                                        float(u), _p(od), _p(op))
+    return bool(r), od, op
+
+
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+def is_fp32(fp32: bool = False) -> bool:
+    return bool(lib(fp32).oracle_is_fp32())

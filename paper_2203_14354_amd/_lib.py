@@ -113,7 +113,7 @@ EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_
            "xp_bvh_stats", "xp_propagate", "xp_propagate_ex", "xp_set_loss_groups",
            "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
            "xp_sample_emission_time", "xp_sample_wavelength", "xp_surface_reflectance",
-           "xp_stream_read",
+           "xp_stream_read", "xp_valu_probe",
            "xp_safety_grid_host", "xp_bvh_build_host", "xp_version"]
 
 _lib = None
@@ -152,6 +152,7 @@ def load():
         "xp_sample_emission_time": (ctypes.c_int, [U64, U64, I64, F, F, F, P, P, P]),
         "xp_sample_wavelength": (ctypes.c_int, [U64, U64, I64, F, F, P, P]),
         "xp_stream_read": (ctypes.c_int, [P, I64, I32, I32, P, P]),
+        "xp_valu_probe": (ctypes.c_int, [I32, I32, I32, P, P]),
         "xp_surface_reflectance": (ctypes.c_int, [I32, F, F, F, F, F, F, I64, P, P, P, P]),
         "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
         "xp_bvh_build_host": (ctypes.c_int, [P, I64, P, I64, P, P, P, I64, P, I64]),

@@ -877,6 +877,15 @@ int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t block
   return XP_OK;
 }
 
+int xp_valu_probe(int32_t kind, int32_t iters, int32_t blocks, float* out, xp_stream stream) {
+  if (kind < 0 || kind > 2 || iters <= 0 || blocks <= 0 || blocks > (1 << 20) || !out)
+    return fail(nullptr, XP_ERR_INVALID_ARG, "bad VALU-probe arguments");
+  const hipError_t e = xp::launch_valu_probe(kind, 0.999999f, 1e-7f, iters, blocks, out,
+                                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launch(valu_probe)");
+  return XP_OK;
+}
+
 int xp_sample_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean_nm, float fwhm_nm,
                          float* out, xp_stream stream) {
   if (n < 0 || (n > 0 && !out) || !(mean_nm >= 0.0f) || !std::isfinite(mean_nm) ||

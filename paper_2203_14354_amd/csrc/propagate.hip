@@ -42,18 +42,65 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   out_t[i] = b.tri >= 0 ? b.t : kInfF;
 }
 
-// streaming read of a buffer, `passes` times with a grid stride (bandwidth probe)
+// streaming read of a buffer, `passes` times with a grid stride (bandwidth
+// probe).  Each thread keeps four independent 16-byte loads in flight, so that
+// the chip holds enough outstanding requests to reach the bandwidth of the
+// level the buffer lives in rather than its latency bound.
 __global__ void __launch_bounds__(256) stream_read_kernel(const float4* __restrict__ buf, int64_t n,
                                                           int32_t passes, float* out) {
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  float acc = 0.0f;
-  for (int32_t k = 0; k < passes; ++k)
-    for (int64_t i = gid; i < n; i += stride) {
-      const float4 v = buf[i];
-      acc += (v.x + v.y) + (v.z + v.w);
+  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+  for (int32_t k = 0; k < passes; ++k) {
+    int64_t i = gid;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      const float4 v0 = buf[i], v1 = buf[i + stride], v2 = buf[i + 2 * stride],
+                   v3 = buf[i + 3 * stride];
+      acc0 += (v0.x + v0.y) + (v0.z + v0.w);
+      acc1 += (v1.x + v1.y) + (v1.z + v1.w);
+      acc2 += (v2.x + v2.y) + (v2.z + v2.w);
+      acc3 += (v3.x + v3.y) + (v3.z + v3.w);
     }
-  out[gid] = acc;
+    for (; i < n; i += stride) {
+      const float4 v = buf[i];
+      acc0 += (v.x + v.y) + (v.z + v.w);
+    }
+  }
+  out[gid] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+// VALU issue probe (calibrates the SQ instruction and cycle counters against
+// a known instruction count): every thread runs `iters` iterations of 64
+// steps of one kind on eight independent chains, with scalar loop control.
+// kind 0: FP32 multiply-add (one instruction per step); kind 1: FP32
+// reciprocal, a transcendental (one); kind 2: 32-bit integer xor then add
+// (two).
+template <int kKind>
+__global__ void __launch_bounds__(256) valu_probe_kernel(float m, float c, int32_t iters,
+                                                         float* out) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  float a[8];
+  uint32_t q[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = float(threadIdx.x) * 1e-3f + float(j);
+    q[j] = threadIdx.x + uint32_t(j);
+  }
+  for (int32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (kKind == 0) a[j] = fmaf(a[j], m, c);
+        if (kKind == 1) a[j] = __builtin_amdgcn_rcpf(a[j]);
+        if (kKind == 2) q[j] = (q[j] ^ __float_as_uint(m)) + __float_as_uint(c);
+      }
+    }
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += kKind == 2 ? float(q[j]) : a[j];
+  out[gid] = s;
 }
 
 // emission wavelengths with the transport's random-number schedule (test hook)
@@ -217,6 +264,27 @@ hipError_t launch_stream_read(const void* buf, int64_t n_vec, int32_t passes, in
                               float* out, hipStream_t s) {
   hipLaunchKernelGGL(stream_read_kernel, dim3(uint32_t(blocks)), dim3(256), 0, s,
                      static_cast<const float4*>(buf), n_vec, passes, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu_probe(int32_t kind, float m, float c, int32_t iters, int32_t blocks,
+                             float* out, hipStream_t s) {
+  switch (kind) {
+    case 0:
+      hipLaunchKernelGGL(valu_probe_kernel<0>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
+                         iters, out);
+      break;
+    case 1:
+      hipLaunchKernelGGL(valu_probe_kernel<1>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
+                         iters, out);
+      break;
+    case 2:
+      hipLaunchKernelGGL(valu_probe_kernel<2>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
+                         iters, out);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -200,6 +200,8 @@ hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float t
                                 int32_t* out_singlet, hipStream_t s);
 hipError_t launch_time_quantile(const int32_t* hist, int64_t n_events, int32_t n_bins,
                                 float bin_ns, float q, float* out, hipStream_t s);
+hipError_t launch_valu_probe(int32_t kind, float m, float c, int32_t iters, int32_t blocks,
+                             float* out, hipStream_t s);
 hipError_t launch_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t blocks,
                               float* out, hipStream_t s);
 hipError_t launch_wavelength(uint64_t seed, uint64_t pid0, int64_t n, float mean, float sigma,

@@ -85,3 +85,85 @@ def closed_edges_ok(triangles, oriented=True):
     if len(np.unique(key_dir)) != len(key_dir):
         return False
     return bool(np.isin(key_rev, key_dir).all())
+
+
+def plane_wave_boundary(d, e, N, n1, n_sub, layers=(), lam_nm=174.8):
+    """Reflected and transmitted plane waves of a linearly polarized plane wave
+    meeting a planar stack, from Maxwell's boundary conditions alone: the
+    tangential components of E and of H (proportional to kappa x E in
+    non-magnetic media, kappa the refractive wave vector with
+    kappa . kappa = n^2) are continuous at every interface.  The linear system
+    of those conditions is solved numerically; no Fresnel or Airy formula is
+    used.
+
+    d: unit incident direction, e: incident field (unit, perpendicular to d),
+    N: unit normal pointing back into the incident medium (real index n1);
+    layers: (complex index, thickness in nm) of films from the top down, on a
+    substrate of complex index n_sub.  Returns (d_r, E_r, d_t, E_t): the
+    reflected direction and complex field (incident amplitude 1), and the
+    substrate's (complex) refractive wave vector divided by |n_sub| and field
+    at its top interface."""
+    d, e, N = (np.asarray(x, dtype=np.float64) for x in (d, e, N))
+    z = N / np.linalg.norm(N)
+    dt = d - np.dot(d, z) * z
+    if np.linalg.norm(dt) > 1e-12:
+        x = dt / np.linalg.norm(dt)
+    else:
+        a = np.array([1.0, 0, 0]) if abs(z[0]) < 0.9 else np.array([0, 1.0, 0])
+        x = np.cross(a, z)
+        x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    F = np.stack([x, y, z])           # world -> frame rows
+    df, ef = F @ d, F @ e
+    beta = n1 * df[0]                 # conserved tangential wave number
+    k0 = 2 * math.pi / lam_nm
+    media = [complex(n1)] + [complex(n) for n, _ in layers] + [complex(n_sub)]
+    thick = [0.0] + [float(t) for _, t in layers]
+    zs = np.cumsum([0.0] + [-t for t in thick[1:]])  # interface heights z_0 = 0, z_1, ...
+    qs = [np.sqrt(complex(n * n - beta * beta)) for n in media]  # principal branch
+    L = len(layers)
+    n_unk = 4 * (L + 1)
+    yv = np.array([0, 1.0, 0], dtype=complex)
+
+    def waves(j):
+        """(kappa, unknown index of A or None, z_ref) of the waves of medium j."""
+        up = np.array([beta, 0, qs[j]], dtype=complex)
+        down = np.array([beta, 0, -qs[j]], dtype=complex)
+        if j == 0:
+            return [(down, None, 0.0), (up, 0, 0.0)]
+        if j == L + 1:
+            return [(down, 2 + 4 * L, zs[j - 1])]
+        b = 2 + 4 * (j - 1)
+        return [(down, b, zs[j - 1]), (up, b + 2, zs[j - 1])]
+
+    M = np.zeros((n_unk, n_unk), dtype=complex)
+    rhs = np.zeros(n_unk, dtype=complex)
+    for m in range(L + 1):
+        rows = slice(4 * m, 4 * m + 4)
+        for j, sign in ((m, 1.0), (m + 1, -1.0)):
+            for kap, idx, zref in waves(j):
+                ph = np.exp(1j * k0 * kap[2] * (zs[m] - zref))
+                if idx is None:  # the known incident wave
+                    E = ef.astype(complex) * ph
+                    H = np.cross(n1 * df.astype(complex), E)
+                    rhs[rows] -= sign * np.array([E[0], E[1], H[0], H[1]])
+                    continue
+                for col, vec in ((idx, yv), (idx + 1, np.cross(yv, kap))):
+                    E = vec * ph
+                    H = np.cross(kap, E)
+                    M[rows, col] += sign * np.array([E[0], E[1], H[0], H[1]])
+    sol = np.linalg.solve(M, rhs)
+    kr = np.array([beta, 0, qs[0]], dtype=complex)
+    kt = np.array([beta, 0, -qs[-1]], dtype=complex)
+    Er = sol[0] * yv + sol[1] * np.cross(yv, kr)
+    Et = sol[2 + 4 * L] * yv + sol[3 + 4 * L] * np.cross(yv, kt)
+    d_r = F.T @ (kr.real / np.linalg.norm(kr.real))
+    return d_r, F.T @ Er, F.T @ (kt / abs(media[-1])), F.T @ Et
+
+
+def poynting_z(kappa, E, N):
+    """Normal component (along N) of the time-averaged energy flux of a plane
+    wave, up to the constant common to all non-magnetic media: Re(E x conj(H))
+    with H = kappa x E."""
+    H = np.cross(kappa, E)
+    return float(np.real(np.dot(np.cross(E, np.conj(H)), N)))
