@@ -179,10 +179,6 @@ typedef struct xp_bvh_options {
                               tests one triangle and visits one node, and single-triangle
                               leaves keep the triangle tests fewest) */
   int32_t sah_bins;        /* SAH bins per axis, 4..64 (default 32) */
-  int32_t safety_cells;    /* cells of the safety grid along the mesh's longest extent,
-                              0..512 (0 = no grid, also when opts is NULL).  A step whose free
-                              path is shorter than the grid's distance bound skips the
-                              closest-hit search; results are identical either way */
   float split_budget;      /* triangles whose box is more than twice the least box a planar
                               piece of their area and orientation needs (long slivers,
                               fans) are clipped into pieces with tighter boxes, the most
@@ -200,8 +196,6 @@ typedef struct xp_bvh_stats {
   int32_t max_stack;       /* worst-case traversal stack entries */
   int64_t node_bytes, triangle_bytes;
   double build_seconds;
-  int32_t safety_dims[3];  /* safety grid cells per axis (0 = no grid) */
-  float safety_cell;       /* cell size (m) */
   int64_t n_references;    /* triangle references in the leaves (n_triangles plus the
                               extra pieces of split triangles); the records are stored per
                               reference: triangle_bytes = 3 * 48 * n_references */
@@ -219,8 +213,8 @@ int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out);
 /* The same host BVH build without a device or a context, for inspecting and
  * testing the structure the kernels traverse.  vtx / tri / nv / nt as in
  * xp_load_mesh (geometric checks only; media, surfaces and sensors are taken
- * as 0 / -1 / -1); opts as in xp_build_bvh (safety_cells is ignored).  Fills
- * *info (build_seconds: this call; safety fields 0) and, when not NULL, copies
+ * as 0 / -1 / -1); opts as in xp_build_bvh.  Fills *info (build_seconds:
+ * this call) and, when not NULL, copies
  *   nodes    info->n_nodes 128-byte nodes, breadth-first, root first:
  *            float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4] (child
  *            boxes, padded outward by 2^-20 relative + 1e-7 m; an empty slot
@@ -360,14 +354,19 @@ typedef struct xp_photon_record {
  *              [0..7] photons per terminal flag (index = flag low byte),
  *              [8] GEOMETRY_ERROR photons, [9] steps, [10] BVH nodes visited,
  *              [11] triangles tested, [12] search lane-slots offered and
- *              [13] used (SIMD utilization of the search), [14] steps whose
- *              search the safety grid skipped, [15] wave interaction phases,
+ *              [13] used (SIMD utilization of the search), [14] reserved (0),
+ *              [15] wave interaction phases,
  *              [16] / [17] wave clock cycles spent in interaction phases / in
  *              search micro-steps (counting mode costs time).
  *   lc         NULL = the context's tuned or default configuration.
  * Errors: XP_ERR_STATE (no BVH / tables), XP_ERR_INVALID_ARG, XP_ERR_HIP.
- * Concurrency: calls on one context use a ring of 64 work counters; at most
- * 64 launches of one context may be in flight at a time. */
+ * Concurrency: eager calls on one context use a ring of 64 work counters; at
+ * most 64 eager launches of one context may be in flight at a time.  A launch
+ * captured into a HIP graph (the stream is capturing) gets a work counter no
+ * other launch uses, so its replays may run beside eager launches of the same
+ * context on other streams; replays of one graph must not overlap each
+ * other.  At most 256 launches per context may be captured
+ * (XP_ERR_UNSUPPORTED beyond). */
 int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
                  int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
                  uint64_t* d_stats, const xp_launch_cfg* lc, xp_stream stream);
@@ -432,11 +431,14 @@ int xp_backward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
 
 /* Pick the fastest launch configuration on a sample of `src` (at most
  * sample_photons photons) by timing hit-map launches (best of three each):
- * block sizes 64 / 256, 0 / 3 BVH levels in LDS, 8 / 16 LDS stack entries,
- * wave_batch 16 / 32 / 48 with the default block_tally, then the fastest of
- * these with block_tally 1 (block_tally is never set to -1: the default keeps
- * the LDS tallies that gradient launches need).  The default configuration
- * is kept unless a candidate is more than 2 % faster on the sample.  Stores
+ * block sizes 64 / 256, no / automatic BVH levels in LDS, 8 / 16 LDS stack
+ * entries and wave_batch 16 / 32 / 48 with the default block_tally; then,
+ * around the fastest so far, 2 / 3 / 4 workgroups per CU (against the
+ * occupancy limit), then refill chunks of 16 / 32 / 128 / 256 photon ids
+ * (against 64); then the fastest with block_tally 1 (block_tally is never set
+ * to -1: the default keeps the LDS tallies that gradient launches need).  The
+ * default configuration is kept unless a candidate is more than 2 % faster
+ * on the sample.  Stores
  * the result in the context (used when lc is NULL) and in *out (may be
  * NULL).  Integer results never depend on the
  * choice.  Synchronizes the stream.  Errors as xp_propagate. */
@@ -495,21 +497,15 @@ int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t block
 /* VALU issue probe for the roofline (not part of the transport): `blocks`
  * workgroups of 256 threads each run `iters` iterations of 64 steps of one
  * kind on eight independent chains (kind 0: one FP32 multiply-add per step,
- * 1: one FP32 reciprocal, 2: a 32-bit integer xor and an add) and write one
- * value per thread to out (device float[blocks * 256]).  A kernel of known
- * instruction count for calibrating the shader-sequencer counters and
- * measuring the issue rate the chip sustains.  Errors: XP_ERR_INVALID_ARG,
+ * 1: one FP32 reciprocal, 2: a 32-bit integer xor and an add, 3: an FP32
+ * multiply-add and an independent integer xor and add, 4: an FP32
+ * multiply-add and an independent FP32 reciprocal, 5: a 32 x 32 -> 64-bit
+ * integer multiply-add and a move) and write one value per thread to out (device
+ * float[blocks * 256]).  Kernels of known instruction count for calibrating
+ * the shader-sequencer counters and measuring the issue rate the chip
+ * sustains for each instruction mix.  Errors: XP_ERR_INVALID_ARG,
  * XP_ERR_HIP. */
 int xp_valu_probe(int32_t kind, int32_t iters, int32_t blocks, float* out, xp_stream stream);
-
-/* Host-only (no device needed): build the safety grid of a mesh (host arrays)
- * as xp_build_bvh does.  out_dims int32[3] receives the cells per axis,
- * out_lo float[3] the grid origin, *out_cell the cell size; out_values
- * (float[dims product], may be NULL to query the size) the per-cell distance
- * lower bounds, x fastest.  Errors: XP_ERR_INVALID_ARG, XP_ERR_MESH. */
-int xp_safety_grid_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
-                        int32_t cells_longest, int32_t* out_dims, float* out_lo, float* out_cell,
-                        float* out_values);
 
 /* Library version string. */
 const char* xp_version(void);

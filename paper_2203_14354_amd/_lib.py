@@ -45,15 +45,14 @@ class Surface(ctypes.Structure):
 
 class BvhOptions(ctypes.Structure):
     _fields_ = [("max_leaf_size", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
-                ("safety_cells", ctypes.c_int32), ("split_budget", ctypes.c_float)]
+                ("split_budget", ctypes.c_float)]
 
 
 class BvhInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
                 ("depth", ctypes.c_int32), ("max_stack", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int64), ("triangle_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double), ("safety_dims", ctypes.c_int32 * 3),
-                ("safety_cell", ctypes.c_float), ("n_references", ctypes.c_int64)]
+                ("build_seconds", ctypes.c_double), ("n_references", ctypes.c_int64)]
 
 
 class Sources(ctypes.Structure):
@@ -114,7 +113,7 @@ EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_
            "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
            "xp_sample_emission_time", "xp_sample_wavelength", "xp_surface_reflectance",
            "xp_stream_read", "xp_valu_probe",
-           "xp_safety_grid_host", "xp_bvh_build_host", "xp_version"]
+           "xp_bvh_build_host", "xp_version"]
 
 _lib = None
 
@@ -154,7 +153,6 @@ def load():
         "xp_stream_read": (ctypes.c_int, [P, I64, I32, I32, P, P]),
         "xp_valu_probe": (ctypes.c_int, [I32, I32, I32, P, P]),
         "xp_surface_reflectance": (ctypes.c_int, [I32, F, F, F, F, F, F, I64, P, P, P, P]),
-        "xp_safety_grid_host": (ctypes.c_int, [P, I64, P, I64, I32, P, P, P, P]),
         "xp_bvh_build_host": (ctypes.c_int, [P, I64, P, I64, P, P, P, I64, P, I64]),
         "xp_version": (ctypes.c_char_p, []),
     }

@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxephot.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-HOST_SOURCES = ["api.cpp", "bvh.cpp", "safety.cpp"]
+HOST_SOURCES = ["api.cpp", "bvh.cpp"]
 DEVICE_SOURCES = ["propagate.hip", "propagate_tally.hip"]
 ARCH = "gfx950"
 

@@ -42,9 +42,9 @@ struct xp_context {
   int32_t d_channel_len = 0;
   int32_t* d_tri_group = nullptr;       // loss group per mesh triangle
   int32_t n_groups = 0;                 // 0: no loss groups set
-  unsigned long long* d_counters = nullptr;
-  float* d_safety = nullptr;            // safety grid values
-  xp::SafetyGrid safety;                // grid geometry (values released after upload)
+  unsigned long long* d_counters = nullptr;        // ring of kCounterRing eager-launch counters
+  unsigned long long* d_graph_counters = nullptr;  // one per launch captured in a graph
+  int32_t graph_next = 0;                          // graph counters handed out
   int32_t* d_stack_overflow = nullptr;  // per-lane spill slots of the traversal stack
   int64_t stack_overflow_lanes = 0;
   unsigned ring_next = 0;
@@ -207,12 +207,6 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   a.stack_lds = lc.stack_lds;
   a.stack_total = ctx->bvh.max_stack;
   a.stack_overflow = ctx->d_stack_overflow;
-  a.safety = ctx->d_safety;
-  for (int k = 0; k < 3; ++k) {
-    a.sg_n[k] = ctx->safety.n[k];
-    a.sg_lo[k] = ctx->safety.lo[k];
-  }
-  a.sg_inv_cell = ctx->safety.inv_cell;
   a.n_channels = ctx->n_channels;
   a.n_sensors = ctx->max_sensor + 1;
   a.src_kind = src->kind;
@@ -381,9 +375,22 @@ void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_l
 int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records, bool count,
            const xp_launch_cfg& lc, int grid, hipStream_t s) {
   if (a.n_photons == 0) return XP_OK;
-  unsigned long long* counter = ctx->d_counters + (ctx->ring_next++ % xp::kCounterRing);
+  // A launch captured in a graph keeps its counter for every replay, so it
+  // gets one that no other launch will use; eager launches reuse the ring.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
+  unsigned long long* counter;
+  if (cap == hipStreamCaptureStatusActive) {
+    if (ctx->graph_next >= xp::kGraphCounters)
+      return fail(ctx, XP_ERR_UNSUPPORTED, "more than " + std::to_string(xp::kGraphCounters) +
+                                               " launches captured in graphs on this context");
+    counter = ctx->d_graph_counters + ctx->graph_next++;
+  } else {
+    counter = ctx->d_counters + (ctx->ring_next++ % xp::kCounterRing);
+  }
   a.work_counter = counter;
-  hipError_t e = xp::launch_reset(counter, s);
+  e = xp::launch_reset(counter, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(reset)");
   e = xp::launch_propagate(a, mode, grad, records, count, lc.block_size, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(propagate)");
@@ -418,11 +425,13 @@ int xp_context_create(int hip_device, xp_context** out) {
     ctx->device = hip_device;
     ctx->n_cu = prop.multiProcessorCount;
     ctx->max_lds = prop.sharedMemPerBlock;
-    e = hipMalloc(&ctx->d_counters, xp::kCounterRing * sizeof(unsigned long long));
+    e = hipMalloc(&ctx->d_counters,
+                  (xp::kCounterRing + xp::kGraphCounters) * sizeof(unsigned long long));
     if (e != hipSuccess) {
       delete ctx;
       return hip_fail(nullptr, e, "hipMalloc(work counters)");
     }
+    ctx->d_graph_counters = ctx->d_counters + xp::kCounterRing;
     *out = ctx;
     return XP_OK;
   } catch (const std::bad_alloc&) {
@@ -441,7 +450,6 @@ void xp_context_destroy(xp_context* ctx) {
   dfree(ctx->d_tri_group);
   dfree(ctx->d_counters);
   dfree(ctx->d_stack_overflow);
-  dfree(ctx->d_safety);
   delete ctx;
 }
 
@@ -473,17 +481,14 @@ int check_geometry(xp_context* ctx, const float* vtx, int64_t nv, const int32_t*
 
 // BVH build options with their defaults filled in.
 int parse_bvh_options(xp_context* ctx, const xp_bvh_options* opts, int& leaf, int& bins,
-                      int& scells, double& split_budget) {
+                      double& split_budget) {
   leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
   bins = opts && opts->sah_bins ? opts->sah_bins : 32;
-  scells = opts ? opts->safety_cells : 0;
   const float sb = opts ? opts->split_budget : 0.0f;
   if (!(sb <= 4.0f)) return fail(ctx, XP_ERR_INVALID_ARG, "split_budget must be at most 4");
   split_budget = sb == 0.0f ? xp::kDefaultSplitBudget : (sb < 0.0f ? 0.0 : double(sb));
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
-  if (scells < 0 || scells > 512)
-    return fail(ctx, XP_ERR_INVALID_ARG, "safety_cells must be in 0..512");
   return XP_OK;
 }
 
@@ -641,9 +646,9 @@ int xp_set_channel_map(xp_context* ctx, const int32_t* channel_of_sensor, int32_
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   if (!ctx) return fail(nullptr, XP_ERR_INVALID_ARG, "null context");
   if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
-  int leaf = 1, bins = 32, scells = 0;
+  int leaf = 1, bins = 32;
   double split_budget = 0.0;
-  const int oc = parse_bvh_options(ctx, opts, leaf, bins, scells, split_budget);
+  const int oc = parse_bvh_options(ctx, opts, leaf, bins, split_budget);
   if (oc != XP_OK) return oc;
   if (int64_t(ctx->mat_in.size()) >= (int64_t(1) << 28))
     return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
@@ -659,9 +664,6 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
                         split_budget, r, err))
       return fail(ctx, XP_ERR_MESH, err);
     if (r.max_stack > 512) return fail(ctx, XP_ERR_UNSUPPORTED, "BVH too deep");
-    xp::SafetyGrid sg;
-    if (!xp::build_safety_grid(ctx->vtx.data(), ctx->tri.data(), nt, scells, sg, err))
-      return fail(ctx, XP_ERR_UNSUPPORTED, err);
     DeviceGuard g(ctx->device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     ctx->bvh_built = false;
@@ -678,18 +680,6 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(triangles)");
     // spill slots for every lane that can be resident at once (allocated here,
     // never inside a launch, so that launches can be captured in a graph)
-    dfree(ctx->d_safety);
-    ctx->safety = xp::SafetyGrid();
-    if (!sg.values.empty()) {
-      e = hipMalloc(&ctx->d_safety, sg.values.size() * sizeof(float));
-      if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(safety grid)");
-      e = hipMemcpy(ctx->d_safety, sg.values.data(), sg.values.size() * sizeof(float),
-                    hipMemcpyHostToDevice);
-      if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(safety grid)");
-      sg.values.clear();
-      sg.values.shrink_to_fit();
-      ctx->safety = sg;
-    }
     dfree(ctx->d_stack_overflow);
     ctx->stack_overflow_lanes = int64_t(ctx->n_cu) * xp::kMaxThreadsPerCu;
     e = hipMalloc(&ctx->d_stack_overflow,
@@ -706,8 +696,6 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
     ctx->stats.node_bytes = int64_t(r.nodes.size() * sizeof(xp::Node4));
     ctx->stats.triangle_bytes = int64_t(r.tris.size() * sizeof(xp::TriRec));
     ctx->stats.build_seconds = secs;
-    for (int k = 0; k < 3; ++k) ctx->stats.safety_dims[k] = ctx->safety.n[k];
-    ctx->stats.safety_cell = ctx->safety.inv_cell > 0 ? 1.0f / ctx->safety.inv_cell : 0.0f;
     r.nodes.clear();
     r.nodes.shrink_to_fit();
     r.tris.clear();
@@ -729,9 +717,9 @@ int xp_bvh_build_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t 
   try {
     int rc = check_geometry(nullptr, vtx, nv, tri, nt);
     if (rc != XP_OK) return rc;
-    int leaf = 1, bins = 32, scells = 0;
+    int leaf = 1, bins = 32;
     double split_budget = 0.0;
-    rc = parse_bvh_options(nullptr, opts, leaf, bins, scells, split_budget);
+    rc = parse_bvh_options(nullptr, opts, leaf, bins, split_budget);
     if (rc != XP_OK) return rc;
     if (nt >= (int64_t(1) << 28))
       return fail(nullptr, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
@@ -777,10 +765,15 @@ int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out) {
   return XP_OK;
 }
 
-int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
-                    int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
-                    uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
-                    xp_stream stream) {
+}  // extern "C"
+
+namespace {
+
+// Forward launch of xp_propagate_ex.
+int propagate_forward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                      int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                      uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
+                      xp_stream stream) {
   try {
     xp::LaunchArgs a;
     xp_launch_cfg cfg;
@@ -820,6 +813,17 @@ int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params*
   } catch (...) {
     return fail(ctx, XP_ERR_HIP, "unexpected exception");
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                    int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                    uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
+                    xp_stream stream) {
+  return propagate_forward(ctx, src, rp, d_hit_map, d_grad, d_records, d_stats, extra, lc, stream);
 }
 
 int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp, int32_t* d_hit_map,
@@ -878,7 +882,7 @@ int xp_stream_read(const void* buf, int64_t n_vec, int32_t passes, int32_t block
 }
 
 int xp_valu_probe(int32_t kind, int32_t iters, int32_t blocks, float* out, xp_stream stream) {
-  if (kind < 0 || kind > 2 || iters <= 0 || blocks <= 0 || blocks > (1 << 20) || !out)
+  if (kind < 0 || kind > 5 || iters <= 0 || blocks <= 0 || blocks > (1 << 20) || !out)
     return fail(nullptr, XP_ERR_INVALID_ARG, "bad VALU-probe arguments");
   const hipError_t e = xp::launch_valu_probe(kind, 0.999999f, 1e-7f, iters, blocks, out,
                                              static_cast<hipStream_t>(stream));
@@ -978,63 +982,83 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
-    float best_ms = 1e30f, default_ms = 1e30f;
-    xp_launch_cfg best = default_cfg();
     const xp_launch_cfg dflt = default_cfg();
     int rc = XP_OK;
-    std::vector<xp_launch_cfg> cands;
-    for (int b : {64, 256})
-      for (int l : {0, -1})
-        for (int sl : {8, 16})
-          for (int wb : {16, 32, 48}) cands.push_back(xp_launch_cfg{b, 0, 64, l, sl, wb, 0});
-    // then the fastest of these with the block tallies forced on (the default
-    // keeps them for small hit maps; the timing runs tally hits only, so it
-    // never turns them off for launches that also tally gradients)
-    const size_t n_plain = cands.size();
-    for (size_t ci = 0; ci <= n_plain; ++ci) {
-      if (ci == n_plain) {
-        if (best_ms >= 1e30f) break;
-        xp_launch_cfg on = best;
-        on.block_tally = 1;
-        on.blocks_per_cu = 0;
-        cands.push_back(on);
-      }
-      const xp_launch_cfg cand = cands[ci];
+    // best of three timings of one candidate; false if it does not fit the
+    // device (skipped) or on an error (rc set)
+    auto time_cfg = [&](const xp_launch_cfg& cand, float& ms_out) -> bool {
       xp::LaunchArgs a;
       xp_launch_cfg cfg;
       int grid = 0;
       rc = prepare(ctx, &sample, rp, &cand, a, cfg, grid);
       if (rc == XP_ERR_UNSUPPORTED) {  // does not fit this device: skip the candidate
         rc = XP_OK;
-        continue;
+        return false;
       }
-      if (rc != XP_OK) break;
+      if (rc != XP_OK) return false;
       a.hit_map = d_map;
       choose_block_tally(ctx, &sample, cfg, true, false, false, false, a);
       float ms_best = 1e30f;
-      for (int rep = 0; rep < 3 && rc == XP_OK; ++rep) {
+      for (int rep = 0; rep < 3; ++rep) {
         (void)hipEventRecord(t0, s);
         rc = launch(ctx, a, xp::kForward, false, false, false, cfg, grid, s);
-        if (rc != XP_OK) break;
+        if (rc != XP_OK) return false;
         (void)hipEventRecord(t1, s);
         e = hipEventSynchronize(t1);
         if (e != hipSuccess) {
           rc = hip_fail(ctx, e, "autotune run");
-          break;
+          return false;
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, t0, t1);
         ms_best = std::min(ms_best, ms);
       }
-      if (rc != XP_OK) break;
-      if (cand.block_size == dflt.block_size && cand.lds_levels == dflt.lds_levels &&
+      ms_out = ms_best;
+      return true;
+    };
+    float best_ms = 1e30f, default_ms = 1e30f;
+    xp_launch_cfg best = dflt;
+    auto consider = [&](const xp_launch_cfg& cand) {
+      float ms = 0.0f;
+      if (!time_cfg(cand, ms)) return;
+      if (cand.block_size == dflt.block_size && cand.blocks_per_cu == dflt.blocks_per_cu &&
+          cand.chunk == dflt.chunk && cand.lds_levels == dflt.lds_levels &&
           cand.stack_lds == dflt.stack_lds && cand.wave_batch == dflt.wave_batch &&
           cand.block_tally == dflt.block_tally)
-        default_ms = ms_best;
-      if (ms_best < best_ms) {
-        best_ms = ms_best;
-        best = cfg;
+        default_ms = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
       }
+    };
+    // stage 1: block size, staged BVH levels, LDS stack ring, interaction batch
+    for (int b : {64, 256})
+      for (int l : {0, -1})
+        for (int sl : {8, 16})
+          for (int wb : {16, 32, 48}) {
+            if (rc == XP_OK) consider(xp_launch_cfg{b, 0, 64, l, sl, wb, 0});
+          }
+    // stage 2: workgroups per CU below the occupancy limit (0 = the limit),
+    // then photon ids per refill, each around the best so far
+    const xp_launch_cfg s1 = best;
+    for (int bpc : {2, 3, 4}) {
+      xp_launch_cfg c = s1;
+      c.blocks_per_cu = bpc;
+      if (rc == XP_OK) consider(c);
+    }
+    const xp_launch_cfg s2 = best;
+    for (int ch : {16, 32, 128, 256}) {
+      xp_launch_cfg c = s2;
+      c.chunk = ch;
+      if (rc == XP_OK) consider(c);
+    }
+    // then the best with the block tallies forced on (the default keeps them
+    // for small hit maps; the timing runs tally hits only, so it never turns
+    // them off for launches that also tally gradients)
+    if (rc == XP_OK && best_ms < 1e30f) {
+      xp_launch_cfg on = best;
+      on.block_tally = 1;
+      consider(on);
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
@@ -1042,8 +1066,8 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
     if (rc != XP_OK) return rc;
     // the default unless a candidate is clearly faster: timings on a sample
     // of a few milliseconds do not separate configurations within ~2 %
+    // (blocks_per_cu 0 is re-derived from the occupancy at launch)
     if (default_ms < 1e30f && best_ms > 0.98f * default_ms) best = dflt;
-    best.blocks_per_cu = 0;  // re-derived from occupancy at launch
     ctx->tuned_cfg = best;
     ctx->tuned = true;
     if (out) *out = best;
@@ -1070,31 +1094,6 @@ int xp_closest_hit(xp_context* ctx, int64_t n, const float* orig, const float* d
       skip, tmin, tmax, brute, out_tri, out_t, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "launch(closest_hit)");
   return XP_OK;
-}
-
-int xp_safety_grid_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t nt,
-                        int32_t cells_longest, int32_t* out_dims, float* out_lo, float* out_cell,
-                        float* out_values) {
-  if (!vtx || !tri || nv <= 0 || nt <= 0 || !out_dims || !out_lo || !out_cell ||
-      cells_longest < 1 || cells_longest > 512)
-    return fail(nullptr, XP_ERR_INVALID_ARG, "bad safety-grid arguments");
-  for (int64_t i = 0; i < 3 * nt; ++i)
-    if (tri[i] < 0 || tri[i] >= nv) return fail(nullptr, XP_ERR_MESH, "vertex index out of range");
-  try {
-    xp::SafetyGrid g;
-    std::string err;
-    if (!xp::build_safety_grid(vtx, tri, nt, cells_longest, g, err))
-      return fail(nullptr, XP_ERR_MESH, err);
-    for (int k = 0; k < 3; ++k) {
-      out_dims[k] = g.n[k];
-      out_lo[k] = g.lo[k];
-    }
-    *out_cell = 1.0f / g.inv_cell;
-    if (out_values) std::copy(g.values.begin(), g.values.end(), out_values);
-    return XP_OK;
-  } catch (...) {
-    return fail(nullptr, XP_ERR_OOM, "host allocation failed");
-  }
 }
 
 int xp_sample(int32_t kind, uint64_t seed, uint64_t pid0, int64_t n, const float* in_dir,

@@ -5,6 +5,7 @@
 #include "transport.h"
 
 namespace xp {
+
 namespace {
 
 __global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
@@ -28,7 +29,7 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   const f3 d{dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
   const int32_t sk = skip ? skip[i] : -1;
   Best b{tmax, -1, -1};
-  Counters c{0u, 0u, 0u, 0u, 0u};
+  Counters c{0u, 0u, 0u, 0u};
   bool ok = true;
   if (brute) {
     const RayW r = make_ray(o, d, n_tris);
@@ -71,35 +72,54 @@ __global__ void __launch_bounds__(256) stream_read_kernel(const float4* __restri
 
 // VALU issue probe (calibrates the SQ instruction and cycle counters against
 // a known instruction count): every thread runs `iters` iterations of 64
-// steps of one kind on eight independent chains, with scalar loop control.
-// kind 0: FP32 multiply-add (one instruction per step); kind 1: FP32
-// reciprocal, a transcendental (one); kind 2: 32-bit integer xor then add
-// (two).
+// steps on eight independent chains, with scalar loop control.  Kinds, with
+// the VALU instructions per step:
+//   0 FP32 multiply-add (one);  1 FP32 reciprocal, a transcendental (one);
+//   2 32-bit integer xor then add (two);
+//   3 an FP32 multiply-add and an independent integer xor and add (three);
+//   4 an FP32 multiply-add and an independent FP32 reciprocal (two);
+//   5 a 32 x 32 -> 64-bit integer multiply-add (Philox's product) and a move
+//     of its high half (two).
+// Kinds 3 and 4 mix instruction types within a wave, the case in which the
+// counters of the transport kernel show two VALU instructions issued in one
+// cycle group.
 template <int kKind>
 __global__ void __launch_bounds__(256) valu_probe_kernel(float m, float c, int32_t iters,
                                                          float* out) {
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  float a[8];
+  float a[8], b[8];
   uint32_t q[8];
+  uint64_t w[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     a[j] = float(threadIdx.x) * 1e-3f + float(j);
+    b[j] = 1.0f + float(j);
     q[j] = threadIdx.x + uint32_t(j);
+    w[j] = uint64_t(threadIdx.x) * 3u + uint64_t(j);
   }
+  const uint32_t mb = __float_as_uint(m), cb = __float_as_uint(c);
   for (int32_t it = 0; it < iters; ++it) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        if (kKind == 0) a[j] = fmaf(a[j], m, c);
-        if (kKind == 1) a[j] = __builtin_amdgcn_rcpf(a[j]);
-        if (kKind == 2) q[j] = (q[j] ^ __float_as_uint(m)) + __float_as_uint(c);
+        if (kKind == 0 || kKind == 3 || kKind == 4) a[j] = fmaf(a[j], m, c);
+        if (kKind == 1 || kKind == 4) b[j] = __builtin_amdgcn_rcpf(b[j]);
+        if (kKind == 2 || kKind == 3) q[j] = (q[j] ^ mb) + cb;
+        if (kKind == 5) w[j] = uint64_t(uint32_t(w[j])) * mb + (w[j] >> 32);
       }
     }
   }
   float s = 0.0f;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) s += kKind == 2 ? float(q[j]) : a[j];
+  for (int j = 0; j < 8; ++j) {
+    if (kKind == 0) s += a[j];
+    if (kKind == 1) s += b[j];
+    if (kKind == 2) s += float(q[j]);
+    if (kKind == 3) s += a[j] + float(q[j]);
+    if (kKind == 4) s += a[j] + b[j];
+    if (kKind == 5) s += float(uint32_t(w[j]));
+  }
   out[gid] = s;
 }
 
@@ -184,11 +204,7 @@ __global__ void sample_kernel(int32_t kind, uint32_t s0, uint32_t s1, uint64_t p
     p.pol = f3{in_pol[3 * i], in_pol[3 * i + 1], in_pol[3 * i + 2]};
     rayleigh(p, s0, s1, pid, 1u);
   } else {
-    const R4 q = draw(s0, s1, pid, 0u, 1u);
-    const float rr = cyl_r * sqrtf(q.u0);
-    float sp, cp;
-    sincospif(2.0f * q.u1, &sp, &cp);
-    p.dir = {rr * cp, rr * sp, zlo + (zhi - zlo) * q.u2};
+    p.dir = cylinder_point(s0, s1, pid, cyl_r, zlo, zhi);  // the transport's emission code
   }
   out_dir[3 * i] = p.dir.x; out_dir[3 * i + 1] = p.dir.y; out_dir[3 * i + 2] = p.dir.z;
   out_pol[3 * i] = p.pol.x; out_pol[3 * i + 1] = p.pol.y; out_pol[3 * i + 2] = p.pol.z;
@@ -269,19 +285,14 @@ hipError_t launch_stream_read(const void* buf, int64_t n_vec, int32_t passes, in
 
 hipError_t launch_valu_probe(int32_t kind, float m, float c, int32_t iters, int32_t blocks,
                              float* out, hipStream_t s) {
+  const dim3 grid{uint32_t(blocks)}, block{256u};
   switch (kind) {
-    case 0:
-      hipLaunchKernelGGL(valu_probe_kernel<0>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
-                         iters, out);
-      break;
-    case 1:
-      hipLaunchKernelGGL(valu_probe_kernel<1>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
-                         iters, out);
-      break;
-    case 2:
-      hipLaunchKernelGGL(valu_probe_kernel<2>, dim3(uint32_t(blocks)), dim3(256), 0, s, m, c,
-                         iters, out);
-      break;
+    case 0: hipLaunchKernelGGL(valu_probe_kernel<0>, grid, block, 0, s, m, c, iters, out); break;
+    case 1: hipLaunchKernelGGL(valu_probe_kernel<1>, grid, block, 0, s, m, c, iters, out); break;
+    case 2: hipLaunchKernelGGL(valu_probe_kernel<2>, grid, block, 0, s, m, c, iters, out); break;
+    case 3: hipLaunchKernelGGL(valu_probe_kernel<3>, grid, block, 0, s, m, c, iters, out); break;
+    case 4: hipLaunchKernelGGL(valu_probe_kernel<4>, grid, block, 0, s, m, c, iters, out); break;
+    case 5: hipLaunchKernelGGL(valu_probe_kernel<5>, grid, block, 0, s, m, c, iters, out); break;
     default:
       return hipErrorInvalidValue;
   }

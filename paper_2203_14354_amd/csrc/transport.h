@@ -432,7 +432,6 @@ __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, i
 struct Counters {
   uint32_t nodes, tris;
   uint32_t slots, busy;  // search lane slots offered / used (SIMD utilization)
-  uint32_t skipped;      // searches skipped by the safety grid
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
@@ -678,6 +677,17 @@ __device__ __forceinline__ float emission_wavelength(uint32_t s0, uint32_t s1, u
   return mean + sigma * sqrtf(-2.0f * logf(r.u0)) * cospif(2.0f * r.u1);
 }
 
+// Uniform point of the cylinder r <= cyl_r, zlo <= z <= zhi: Philox block
+// (step 0, sub 1), r = cyl_r sqrt(u0), phi = 2 pi u1, z = zlo + (zhi - zlo) u2.
+__device__ __forceinline__ f3 cylinder_point(uint32_t s0, uint32_t s1, uint64_t pid, float cyl_r,
+                                             float zlo, float zhi) {
+  const R4 q = draw(s0, s1, pid, 0u, 1u);
+  const float rr = cyl_r * hw_sqrt(q.u0);
+  float sp, cp;
+  sincos_rev(q.u1, sp, cp);
+  return {rr * cp, rr * sp, zlo + (zhi - zlo) * q.u2};
+}
+
 __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
   p.time = 0.0f;
   p.wavelength = emission_wavelength(a.seed_lo, a.seed_hi, pid, a.wl_mean, a.wl_sigma);
@@ -711,11 +721,7 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
     p.pos = {a.positions[3 * s], a.positions[3 * s + 1], a.positions[3 * s + 2]};
     p.event = a.per_source_events ? int32_t(s) : 0;
   } else {
-    const R4 q = draw(a.seed_lo, a.seed_hi, pid, 0u, 1u);
-    const float rr = a.cyl_r * hw_sqrt(q.u0);
-    float sp, cp;
-    sincos_rev(q.u1, sp, cp);
-    p.pos = {rr * cp, rr * sp, a.cyl_zlo + (a.cyl_zhi - a.cyl_zlo) * q.u2};
+    p.pos = cylinder_point(a.seed_lo, a.seed_hi, pid, a.cyl_r, a.cyl_zlo, a.cyl_zhi);
   }
 }
 
@@ -736,19 +742,6 @@ __device__ __forceinline__ StepDraw begin_step(Photon& p, const LaunchArgs& a, u
   sd.d_sca = isinf(m.ray_len) ? kInfF : -m.ray_len * logf(r.u1);
   sd.u2 = r.u2;
   return sd;
-}
-
-// Lower bound of the distance from p to every triangle (0 outside the grid or
-// without one).
-__device__ __forceinline__ float safety_at(const LaunchArgs& a, f3 p) {
-  if (a.safety == nullptr) return 0.0f;
-  const float fx = (p.x - a.sg_lo[0]) * a.sg_inv_cell;
-  const float fy = (p.y - a.sg_lo[1]) * a.sg_inv_cell;
-  const float fz = (p.z - a.sg_lo[2]) * a.sg_inv_cell;
-  if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f)) return 0.0f;
-  const int32_t x = int32_t(fx), y = int32_t(fy), z = int32_t(fz);
-  if (x >= a.sg_n[0] || y >= a.sg_n[1] || z >= a.sg_n[2]) return 0.0f;
-  return a.safety[(int64_t(z) * a.sg_n[1] + y) * a.sg_n[0] + x];
 }
 
 // Finish the step given the closest hit b within min(d_abs, d_sca) (b.tri < 0:
@@ -966,7 +959,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   uint64_t pid = 0;
   uint64_t pool_next = 0, pool_end = 0;
   bool exhausted = false;
-  Counters cnt{0u, 0u, 0u, 0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u};
   uint32_t n_steps = 0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   // search state of the current step
@@ -1120,12 +1113,6 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         stack.sp = 0;
         stack.base = 0;
         if (kCount) n_steps++;
-        // no triangle is closer than the cell's safety distance: a shorter free
-        // path cannot reach one, and the search's answer is "no hit"
-        if (b.t < safety_at(a, p.pos)) {
-          state = kWaiting;
-          if (kCount) cnt.skipped++;
-        }
       }
     }
     // ---- one micro-step of every traversing lane's closest-hit search ----
@@ -1210,14 +1197,12 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
     const unsigned long long s11 = wave_sum_u64(cnt.tris);
     const unsigned long long s12 = wave_sum_u64(cnt.slots);
     const unsigned long long s13 = wave_sum_u64(cnt.busy);
-    const unsigned long long s14 = wave_sum_u64(cnt.skipped);
     if (lane == 0) {
       atomicAdd(&blk_stats[9], s9);
       atomicAdd(&blk_stats[10], s10);
       atomicAdd(&blk_stats[11], s11);
       atomicAdd(&blk_stats[12], s12);
       atomicAdd(&blk_stats[13], s13);
-      atomicAdd(&blk_stats[14], s14);
       atomicAdd(&blk_stats[15], n_phases);
       atomicAdd(&blk_stats[16], cyc_phase);
       atomicAdd(&blk_stats[17], cyc_search);

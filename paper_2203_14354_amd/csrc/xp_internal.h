@@ -14,7 +14,8 @@ namespace xp {
 
 constexpr int kMaxMaterials = 8;
 constexpr int kMaxSurfaces = 16;
-constexpr int kCounterRing = 64;
+constexpr int kCounterRing = 64;      // work counters of eager launches, reused in turn
+constexpr int kGraphCounters = 256;   // work counters of launches captured in graphs
 constexpr int kStatsWords = 24;
 constexpr int kStackLds = 16;        // LDS ring entries per lane
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
@@ -92,10 +93,6 @@ struct LaunchArgs {
   int32_t stack_lds;       // LDS ring entries per lane (power of two)
   int32_t stack_total;     // worst-case stack entries of the BVH
   int32_t* stack_overflow; // [stack_total][grid * block] spill slots
-  const float* safety;     // safety grid (nullptr: always search)
-  int32_t sg_n[3];
-  float sg_lo[3];
-  float sg_inv_cell;
   int32_t n_channels;
   int32_t n_sensors;
   // sources
@@ -146,17 +143,6 @@ struct LaunchArgs {
   int32_t n_time_cells;    // events * time bins
   int32_t n_loss_cells;    // (groups + materials) * 8
 };
-
-// Per-cell lower bound of the distance to the nearest triangle (see safety.cpp).
-struct SafetyGrid {
-  std::vector<float> values;  // x fastest, then y, then z
-  int32_t n[3] = {0, 0, 0};
-  float lo[3] = {0.f, 0.f, 0.f};
-  float inv_cell = 0.f;
-};
-
-bool build_safety_grid(const float* vtx, const int32_t* tri, int64_t nt, int cells_longest,
-                       SafetyGrid& out, std::string& err);
 
 struct BvhResult {
   std::vector<Node4> nodes;

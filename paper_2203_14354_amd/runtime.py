@@ -73,7 +73,7 @@ class Detector:
     """A mesh + optical tables + BVH resident on one GPU."""
 
     def __init__(self, mesh, device=0, channel_of_sensor=None, n_channels=None,
-                 max_leaf_size=1, sah_bins=32, safety_cells=0, split_budget=0.0):
+                 max_leaf_size=1, sah_bins=32, split_budget=0.0):
         self.lib = load()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.mesh = mesh
@@ -91,11 +91,10 @@ class Detector:
         else:
             self.n_channels = int(max(mesh.n_sensors, int(mesh.sensor.max()) + 1, 1))
         check(self.lib.xp_build_bvh(self.ctx, ctypes.byref(
-            BvhOptions(max_leaf_size, sah_bins, safety_cells, split_budget))), self.ctx)
+            BvhOptions(max_leaf_size, sah_bins, split_budget))), self.ctx)
         info = BvhInfo()
         check(self.lib.xp_bvh_stats(self.ctx, ctypes.byref(info)), self.ctx)
         self.bvh = {k: getattr(info, k) for k, _ in BvhInfo._fields_}
-        self.bvh["safety_dims"] = list(info.safety_dims)
 
     def _upload_mesh(self, mesh):
         self._mesh_arrays = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
@@ -279,7 +278,7 @@ def bvh_build_host(vertices, triangles, max_leaf_size=1, sah_bins=32, split_budg
     lib = load()
     v = np.ascontiguousarray(vertices, dtype=np.float32).reshape(-1, 3)
     t = np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3)
-    opts = BvhOptions(max_leaf_size, sah_bins, 0, split_budget)
+    opts = BvhOptions(max_leaf_size, sah_bins, split_budget)
     info = BvhInfo()
     args = (_host_ptr(v), len(v), _host_ptr(t), len(t), ctypes.byref(opts), ctypes.byref(info))
     check(lib.xp_bvh_build_host(*args, None, 0, None, 0))
@@ -287,7 +286,6 @@ def bvh_build_host(vertices, triangles, max_leaf_size=1, sah_bins=32, split_budg
     recs = np.zeros(3 * info.n_references, dtype=_lib.TRIREC_DTYPE)
     check(lib.xp_bvh_build_host(*args, _host_ptr(nodes), len(nodes), _host_ptr(recs), len(recs)))
     d = {k: getattr(info, k) for k, _ in BvhInfo._fields_}
-    d["safety_dims"] = list(info.safety_dims)
     return d, nodes, recs
 
 

@@ -276,7 +276,7 @@ def test_host_build_rejects_bad_input():
     import ctypes
     lib = _lib.load()
     info = _lib.BvhInfo()
-    opts = _lib.BvhOptions(1, 32, 0, 0.0)
+    opts = _lib.BvhOptions(1, 32, 0.0)
     vv = np.ascontiguousarray(v, np.float32)
     tt = np.ascontiguousarray(t, np.int32)
     P = ctypes.c_void_p

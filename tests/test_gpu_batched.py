@@ -60,6 +60,44 @@ def test_graph_replay_equals_eager(det):
         assert int(other.sum()) > 0
 
 
+def test_captured_launch_keeps_its_own_work_counter(det):
+    """A launch captured in a graph keeps its work counter for every replay.
+    70 eager launches of the same context (more than its ring of 64 eager
+    counters) run on another stream while the graph replays, each launch at
+    one workgroup per CU so that they share the GPU: no eager launch may take
+    the replay's counter (split or repeated photons would change the maps)."""
+    one = dict(blocks_per_cu=1)
+    big = det.sources(W.small_tpc(photons_per_point=200_000).sources)
+    small = det.sources(W.small_tpc(photons_per_point=2_000).sources)
+    ref_big = det.propagate(big, seed=21, launch=one)["hit_map"].clone()
+    ref_small = det.propagate(small, seed=22, launch=one)["hit_map"].clone()
+    hm = torch.zeros_like(ref_big)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        hm.zero_()
+        det.propagate(big, seed=21, hit_map=hm, launch=one)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        hm.zero_()
+        det.propagate(big, seed=21, hit_map=hm, launch=one)
+    torch.cuda.synchronize()
+    for k in range(3):
+        maps = [torch.zeros_like(ref_small) for _ in range(70)]
+        torch.cuda.synchronize()
+        side.wait_stream(torch.cuda.current_stream())
+        g.replay()
+        with torch.cuda.stream(side):
+            for m in maps:
+                det.propagate(small, seed=22, hit_map=m, launch=one)
+        torch.cuda.synchronize()
+        assert torch.equal(hm, ref_big), k
+        for m in maps:
+            assert torch.equal(m, ref_small), k
+
+
 def test_autotuned_config_gives_identical_results(det):
     wl = W.batched_s1(n_events=256)
     a = det.propagate(wl.sources, seed=1)["hit_map"].clone()
