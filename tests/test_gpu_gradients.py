@@ -1,6 +1,7 @@
 """Gradient tallies on the GPU: per-photon scores against the oracle, the
 backward replay against the contraction of the fused Jacobian, the analytic
-sphere, and common-random-number finite differences."""
+sphere, and common-random-number finite differences at the base point and the
+ends of the paper's systematic ranges."""
 import dataclasses
 import math
 
@@ -110,27 +111,48 @@ def _batched_estimates(det, src, params, seed, n_batches, per_batch, gm=0):
     return torch.stack(H).double().cpu().numpy(), torch.stack(G).cpu().numpy()
 
 
-@pytest.mark.parametrize("p,h", [(0, 5.0), (1, 0.02), (2, 0.01), (3, 0.02)])
-def test_crn_finite_differences(rt, p, h):
-    """d(total hits)/d theta_p: score-function tallies against central finite
-    differences with common random numbers (same seed and photon ids), batch
-    means for the error bars."""
+# (parameter, values moved off the base point): the base point (L_abs 50 m,
+# L_R 0.4 m, R 0.95, T 0.9) for all four parameters, and the ends of the
+# systematic ranges of table tab:lce_sys for the first three
+FD_CASES = [(0, {}), (1, {}), (2, {}), (3, {}),
+            (0, {0: 10.0}), (0, {0: 100.0}), (1, {1: 0.3}), (1, {1: 0.6}),
+            (2, {2: 0.90}), (2, {2: 0.99})]
+
+
+def test_crn_finite_differences(rt):
+    """d(total hits)/d theta_p: the score-function tallies against central
+    finite differences with common random numbers (same seed and photon ids;
+    steps of 2 % for the lengths, 0.005 for R and T), at the base point and at
+    the range ends.  Error bars from 50 batch means of 2e5 photons, the two
+    estimates' variances added (their positive correlation makes this
+    conservative); the pulls must have chi^2/ndf < 1.5 and none may exceed 4."""
     from paper_2203_14354_amd.autograd import base_params
-    nb, per = 40, 100_000
+    nb, per = 50, 200_000
     wl = W.differentiable(n_points=1, photons_per_point=nb * per)
     det = rt.Detector(wl.mesh, device=0)
     ds = det.sources(wl.sources)
-    p0 = base_params(wl.mesh).numpy()
-    _, G = _batched_estimates(det, ds, p0, 11, nb, per)
-    lo, hi = p0.copy(), p0.copy()
-    lo[p] -= h
-    hi[p] += h
-    Hl, _ = _batched_estimates(det, ds, lo, 11, nb, per)
-    Hh, _ = _batched_estimates(det, ds, hi, 11, nb, per)
-    fd = (Hh - Hl) / (2 * h)
-    sc = G[:, p]
-    se = math.sqrt(fd.var(ddof=1) / nb + sc.var(ddof=1) / nb)
-    assert abs(fd.mean() - sc.mean()) < 4 * se + 0.02 * abs(sc.mean()), (fd.mean(), sc.mean(), se)
+    base = base_params(wl.mesh).numpy()
+    pulls = []
+    for p, moved in FD_CASES:
+        x0 = base.copy()
+        for k, v in moved.items():
+            x0[k] = v
+        h = 0.02 * x0[p] if p < 2 else 0.005
+        _, G = _batched_estimates(det, ds, x0, 11, nb, per)
+        lo, hi = x0.copy(), x0.copy()
+        lo[p] -= h
+        hi[p] += h
+        Hl, _ = _batched_estimates(det, ds, lo, 11, nb, per)
+        Hh, _ = _batched_estimates(det, ds, hi, 11, nb, per)
+        fd = (Hh - Hl) / (2 * h)
+        sc = G[:, p]
+        se = math.sqrt(fd.var(ddof=1) / nb + sc.var(ddof=1) / nb)
+        pulls.append((fd.mean() - sc.mean()) / se)
+        print(f"param {p} at {x0.tolist()}: FD {fd.mean():.6g}, score {sc.mean():.6g}, "
+              f"se {se:.3g}, pull {pulls[-1]:+.2f}")
+    pulls = np.array(pulls)
+    assert np.abs(pulls).max() < 4.0, pulls
+    assert (pulls ** 2).mean() < 1.5, pulls
 
 
 def test_block_tallies_equal_global_tallies(rt):

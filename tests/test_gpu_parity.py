@@ -246,8 +246,9 @@ def test_stack_spill_to_global_does_not_change_results(rt):
 def test_darwin_full_size_sampled(rt):
     """The benchmark's workload at its full size (1e8 photons, default launch
     configuration): the hit map with per-photon records equals the plain
-    launch's; the oracle recomputes 2,000 photons sampled over the whole id
-    range one by one."""
+    launch's; the oracle recomputes 100,000 photons, 200 runs of 500
+    consecutive ids spread over the whole id range, and at least 99.9 % of
+    them agree."""
     from paper_2203_14354_amd._lib import RECORD_DTYPE
     mesh = W.darwin()
     det = rt.Detector(mesh, device=0)
@@ -257,20 +258,19 @@ def test_darwin_full_size_sampled(rt):
     out = det.propagate(src, seed=0, records=True)
     torch.cuda.synchronize()
     assert torch.equal(plain, out["hit_map"])
-    idx = np.sort(np.random.default_rng(1).choice(n, 2_000, replace=False))
+    run = 500
+    starts = np.sort(np.random.default_rng(1).choice(n // run, 200, replace=False)) * run
+    idx = (starts[:, None] + np.arange(run)[None, :]).ravel()
     rec = out["records"][torch.from_numpy(idx).cuda()].cpu().numpy()
     gpu = rec.view(RECORD_DTYPE).reshape(-1)
     del out
     torch.cuda.synchronize()
     assert int(plain.sum()) == pytest.approx(0.3254 * n, rel=0.01)
     sc = oracle.Scene(mesh, use_bvh=True)
-    ag = []
-    for k, i in enumerate(idx):
-        r = oracle.run(sc, src, seed=0, i_begin=int(i), i_end=int(i) + 1)["records"][0]
-        g = gpu[k]
-        ag.append(r["flag"] == g["flag"] and r["last_tri"] == g["last_tri"] and
-                  r["steps"] == g["steps"] and r["sensor"] == g["sensor"])
-    assert np.mean(ag) >= 0.998, np.mean(ag)
+    orc = np.concatenate([oracle.run(sc, src, seed=0, i_begin=int(s), i_end=int(s) + run,
+                                     hit_map=False)["records"] for s in starts])
+    ag = agreement(gpu, orc)
+    assert len(ag) == 100_000 and ag.mean() >= 0.999, ag.mean()
 
 
 def test_bvh_leaf_size_does_not_change_results(rt):
@@ -314,33 +314,11 @@ def test_bvh_split_budget_is_validated(rt):
             rt.Detector(W.disk_box(), device=0, split_budget=bad)
 
 
-@pytest.mark.parametrize("geom", ["darwin", "tpc1"])
-def test_safety_grid_does_not_change_results(rt, geom):
-    """Skipping the search where the free path ends before any triangle gives
-    exactly the search's answer: hit maps bit for bit with and without the grid."""
-    if geom == "darwin":
-        mesh = W.darwin()
-        src = W.darwin_tpc(n_photons=2_000_000, mesh=mesh).sources
-    else:
-        mesh = W.tpc1()
-        src = W.small_tpc(photons_per_point=100_000).sources
-    with_grid = rt.Detector(mesh, device=0, safety_cells=128)
-    without = rt.Detector(mesh, device=0, safety_cells=0)
-    assert min(with_grid.bvh["safety_dims"]) > 0 and without.bvh["safety_dims"] == [0, 0, 0]
-    a = with_grid.propagate(src, seed=6, stats=True)
-    b = without.propagate(src, seed=6, stats=True)
-    torch.cuda.synchronize()
-    assert torch.equal(a["hit_map"], b["hit_map"])
-    sa, sb = a["stats"].cpu().numpy(), b["stats"].cpu().numpy()
-    assert np.array_equal(sa[:10], sb[:10])  # same terminal flags and step counts
-    assert sb[14] == 0 and sa[14] > 0        # the grid skipped searches
-    if geom == "darwin":
-        assert sa[14] > 0.2 * sa[9]
-
-
-def test_darwin_parity_sampled(rt):
-    """DARWIN-scale mesh: 1e6 photons uniform in the active volume; the oracle
-    recomputes a sample of them one by one."""
+def test_darwin_parity_whole_launch(rt):
+    """DARWIN-scale mesh: 1e6 photons uniform in the active volume, every one
+    of them recomputed by the oracle: >= 99.9 % agree per photon, the integer
+    hit counts of the agreeing photons are identical, and the per-sensor hit
+    maps (1,778 sensors) agree to chi^2/ndf < 1.2."""
     mesh = W.darwin()
     det = rt.Detector(mesh, device=0)
     src = W.darwin_tpc(n_photons=1_000_003, mesh=mesh).sources
@@ -348,21 +326,22 @@ def test_darwin_parity_sampled(rt):
     torch.cuda.synchronize()
     gpu = to_records(out["records"])
     st = out["stats"].cpu().numpy()
+    hm = out["hit_map"].cpu().numpy()
     assert st[1:8].sum() == len(gpu)
-    assert np.array_equal(out["hit_map"].cpu().numpy(), hist_of_detected(gpu, 1, det.n_channels))
+    assert np.array_equal(hm, hist_of_detected(gpu, 1, det.n_channels))
     plain = det.propagate(src, seed=0)["hit_map"]
     torch.cuda.synchronize()
     assert torch.equal(plain, out["hit_map"])
-    sc = oracle.Scene(mesh, use_bvh=True)
-    idx = np.sort(np.random.default_rng(0).choice(len(gpu), 20_000, replace=False))
-    ag = []
-    for i in idx:
-        r = oracle.run(sc, src, seed=0, i_begin=int(i), i_end=int(i) + 1)["records"][0]
-        g = gpu[i]
-        ag.append(r["flag"] == g["flag"] and r["last_tri"] == g["last_tri"] and
-                  r["steps"] == g["steps"] and r["sensor"] == g["sensor"])
+    ref = oracle.run(oracle.Scene(mesh, use_bvh=True), src, seed=0)
+    orc = ref["records"]
+    ag = agreement(gpu, orc)
     # divergences come from FP32 positions within ~1e-7 m of the 0.5 mm strip edges
-    assert np.mean(ag) >= 0.999, np.mean(ag)
+    # and of the edges shared by coplanar fan triangles
+    assert ag.mean() >= 0.999, ag.mean()
+    nch = det.n_channels
+    assert np.array_equal(hist_of_detected(gpu[ag], 1, nch), hist_of_detected(orc[ag], 1, nch))
+    assert int(((hm + ref["hit_map"]) > 0).sum()) == nch
+    assert chi2_ndf(hm, ref["hit_map"]) < 1.2
     # medium inconsistencies need an FP32 position on the wrong side of a surface
     # by more than the restart offset: at most 1e-5 of the photons
     assert st[8] <= 10, st[8]

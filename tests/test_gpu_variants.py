@@ -2,28 +2,35 @@
 the same kernels on reflective electrodes, a single-phase TPC, no bottom
 array and the 4-pi side arrays of 6,480 PMTs or 87,120 SiPMs.
 
-Bars: per photon (3,000 photon ids sampled from a 200,000-photon launch), the
-same terminal flag, final triangle, sensor and step count as the oracle,
-except at most a fraction 5e-5 per step of the photons (FP32 and FP64 part
-where a uniform lies within ~1e-7 of a threshold or a hit within ~1e-7 m of
-an edge, a few chances per step; the DARWIN-scale baseline measures 2.2e-5
-per step at 30 steps per photon, and removing the bottom array triples the
-path lengths); the {top, bottom, side} hit map identical to the histogram of
-the GPU's own photon records.
+Bars, on every photon of a 200,000-photon launch against the oracle: the same
+terminal flag, final triangle, sensor and step count for >= 99.9 % of them;
+the {top, bottom, side} hit maps within chi^2/ndf < 1.2 of the oracle's; the
+hit map identical to the histogram of the GPU's own photon records.
+
+The variant without the bottom array keeps photons longest (42 steps against
+30, most of them reflections off the 0.99 PTFE floor, a fan of 256 wedges
+whose shared edges the FP32 and FP64 searches resolve differently within
+rounding of the edge).  There the oracle's own FP32 build departs from its
+FP64 build on 0.17 % of the photons, and the bar is that rate: the GPU may
+depart from the FP64 oracle no more often than single-precision arithmetic
+itself does (within 4 standard errors).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2203_14354_amd import workloads as W
-from tests.gpu_common import agreement, hist_of_detected, to_records
+from tests.gpu_common import agreement, chi2_ndf, hist_of_detected, to_records
 
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [dict(coating="all"), dict(coating="gate"), dict(single_phase=True),
             dict(bottom_array=False), dict(side_array="pmt2"), dict(side_array="pmt2", fsr=None),
             dict(side_array="sipm", fsr="coated")]
+FP32_BAR = ({"bottom_array": False},)
 
 
 @pytest.fixture(scope="module")
@@ -46,16 +53,17 @@ def test_variant_matches_oracle(rt, kw):
     hm = out["hit_map"].cpu().numpy()
     assert np.array_equal(hm, hist_of_detected(g, 1, 3, channel=ch))
     assert not np.any(g["flag"] & oracle.F_GEOMETRY_ERROR)
-    idx = np.sort(np.random.default_rng(5).choice(n, 3000, replace=False))
-    sc = oracle.Scene(mesh, channel_of_sensor=ch, n_channels=3, use_bvh=True)
-    ag = []
-    for lo in range(0, n, 20_000):
-        sel = idx[(idx >= lo) & (idx < lo + 20_000)]
-        if len(sel) == 0:
-            continue
-        ref = oracle.run(sc, src, seed=12, i_begin=int(sel[0]), i_end=int(sel[-1]) + 1)["records"]
-        ag.append(agreement(g[sel], ref[sel - sel[0]]))
-    ag = np.concatenate(ag)
-    assert len(ag) == 3000
-    steps = float(g["steps"].mean())
-    assert 1.0 - ag.mean() <= 5e-5 * steps, (ag.mean(), steps)
+    ref = oracle.run(oracle.Scene(mesh, channel_of_sensor=ch, n_channels=3, use_bvh=True), src,
+                     seed=12)
+    ag = agreement(g, ref["records"])
+    assert chi2_ndf(hm, ref["hit_map"]) < 1.2
+    assert np.array_equal(hist_of_detected(g[ag], 1, 3, channel=ch),
+                          hist_of_detected(ref["records"][ag], 1, 3, channel=ch))
+    if kw not in FP32_BAR:
+        assert ag.mean() >= 0.999, ag.mean()
+        return
+    r32 = oracle.run(oracle.Scene(mesh, channel_of_sensor=ch, n_channels=3, use_bvh=True,
+                                  fp32=True), src, seed=12, hit_map=False)["records"]
+    a32 = agreement(r32, ref["records"]).mean()
+    se = math.sqrt(a32 * (1 - a32) / n)
+    assert ag.mean() >= a32 - 4 * se, (ag.mean(), a32)
