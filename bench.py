@@ -27,14 +27,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photons propagated/sec on DARWIN-scale TPC mesh; gradient-pass overhead vs forward"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
-# bytes one node visit and one triangle test read: seven of the eight 16-byte
-# vectors of a 128-byte node (boxes and child entries), one 48-byte record
-NODE_BYTES, TRI_BYTES = 112, 48
+# VALU lane operations per second: 256 CUs x 4 SIMDs, each issuing one wave64
+# instruction every 4 cycles (16 lanes per cycle), at 2.4 GHz; the same as the
+# 78.6 TFLOP/s FP32 multiply-add figure counted in instructions instead of flops
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic work per unit (what the method must compute; not what the kernel
+# executes): VALU lane operations of one BVH4 node visit (four slab tests and
+# the ordering of the hits), one watertight triangle test and the rest of a
+# photon-step (free paths, interaction, random numbers), and the bytes a node
+# visit and a triangle test fetch (a 128-B node, a 64-B triangle).
+OPS_NODE, OPS_TRI, OPS_STEP = 64, 35, 150
+NODE_BYTES, TRI_BYTES = 128, 64
 # what decides the profiled launch: the built library (kernel code, BVH
 # construction, launch defaults; the build is deterministic, and comments do
 # not change it) and the Python defaults that choose the BVH options
 PROFILED_FILES = ["paper_2203_14354_amd/libxephot.so", "paper_2203_14354_amd/runtime.py"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "darwin_tpc_hbm_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "darwin_tpc_hbm_traffic.md")
+VALU_FILE = os.path.join(PROFILES, "propagate_darwin_tpc_valu_counters.md")
+L2_FILE = os.path.join(PROFILES, "propagate_darwin_tpc_l2_requests.md")
+STREAM_FILE = os.path.join(PROFILES, "stream_read_bandwidth_probe.md")
 
 
 def kernel_hash() -> str:
@@ -45,20 +57,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(photons_per_launch: int):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources at the same launch size; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+def profile_values(path: str, photons_per_launch=None):
+    """`key: number` lines of a committed rocprofv3 summary.  With
+    photons_per_launch given, None unless the summary was taken on the current
+    library at that launch size."""
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
-    m_hash = re.search(r"library_sha256_16:\s*([0-9a-f]+)", text)
-    m_n = re.search(r"photons_per_launch:\s*(\d+)", text)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_hash and m_n and m_b):
-        return None
-    if m_hash.group(1) != kernel_hash() or int(m_n.group(1)) != photons_per_launch:
-        return None
-    return float(m_b.group(1))
+    vals = {}
+    for m in re.finditer(r"^([a-z0-9_]+):\s*([0-9a-f.eE+-]+)\s*$", open(path).read(), re.M):
+        vals[m.group(1)] = m.group(2)
+    if photons_per_launch is not None:
+        if vals.get("library_sha256_16") != kernel_hash():
+            return None
+        if int(float(vals.get("photons_per_launch", -1))) != photons_per_launch:
+            return None
+    out = {}
+    for k, v in vals.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 def timed_launches(fn, n, torch):
@@ -87,8 +106,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the gradient-overhead and batched measurements")
-    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
+                    help="skip the gradient-overhead, batched, map, timing and spectrum measurements")
     ap.add_argument("--cache-probe", action="store_true",
                     help="only measure streaming-read bandwidth from buffers resident in the L2 "
                          "caches (16 MB), the Infinity Cache (64-192 MB) and HBM (8 GB)")
@@ -148,26 +166,8 @@ def main():
     cnt = det.propagate(ds, seed=args.seed, pid_base=0, stats=True)
     torch.cuda.synchronize()
     st = cnt["stats"].cpu().tolist()
-    n_steps, n_nodes, n_tris = st[9], st[10], st[11]
-    alg_bytes = NODE_BYTES * n_nodes + TRI_BYTES * n_tris
     kern_s = statistics.mean(durations)
-    achieved = alg_bytes / kern_s
-    traffic_bytes = measured_traffic(N)
-    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK,
-                "traffic": None if traffic_bytes is None else traffic_bytes / kern_s / 1e9,
-                "traffic_bytes_per_launch": traffic_bytes,
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "search_lane_utilization": (st[13] / st[12]) if st[12] else None,
-                "kernel": "propagate_kernel<forward>", "avg_launch_s": kern_s}
-    if achieved > HBM_PEAK:
-        # the declared roof is HBM, but the search's nodes and triangle records
-        # (about 100 MB) are read from L2 and the Infinity Cache: `traffic` is
-        # what actually passes L2, and the SQ counters show VALU issue binding
-        roofline["note"] = ("algorithmic bytes per second above the HBM peak: the BVH and "
-                            "triangle records are served by L2 and the Infinity Cache; "
-                            "the kernel is bound by VALU issue")
-
+    roofline = roofline_of(st, kern_s, N)
     extras = {}
     if not args.no_extras:
         extras.update(gradient_overhead(torch, W, Detector, dev))
@@ -175,12 +175,11 @@ def main():
         extras.update(batched_vs_plain(torch, W, Detector, dev))
         extras.update(lce_map_rate(torch, W, dev))
         extras.update(arrival_time_and_losses(torch, W, Detector, mesh, det, dev, args.photons))
-        extras.update(design_variants(torch, W, Detector, dev))
         extras.update(spectrum_cost(torch, W, det, mesh, dev))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(W, mesh, args.seed, args.cpu_sample)
+        cpu = cpu_baseline(W, mesh, args.seed)
 
     line = {
         "metric": METRIC, "value": value, "unit": "photons/s", "n_gpus": 1, "steps": args.steps,
@@ -194,20 +193,72 @@ def main():
                    "bvh_max_stack": det.bvh["max_stack"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "per_launch": {"steps_per_photon": n_steps / N, "photon_steps_per_s": value * n_steps / N,
-                       "nodes_per_step": n_nodes / n_steps,
-                       "triangles_per_step": n_tris / n_steps,
+        "per_launch": {"steps_per_photon": st[9] / N, "photon_steps_per_s": value * st[9] / N,
+                       "nodes_per_step": st[10] / st[9],
+                       "triangles_per_step": st[11] / st[9],
+                       "search_lane_utilization": (st[13] / st[12]) if st[12] else None,
                        "detected_fraction": st[1] / N, "bulk_absorbed_fraction": st[4] / N,
                        "surface_absorbed_fraction": st[3] / N,
-                       "search_skipped_fraction": st[14] / n_steps,
                        "phase_cycle_fraction": st[16] / max(st[16] + st[17], 1),
-                       "lane_steps_per_phase": n_steps / max(st[15], 1),
+                       "lane_steps_per_phase": st[9] / max(st[15], 1),
                        "geometry_errors": st[8], "escaped": st[5], "max_steps": st[6],
                        "nan_aborts": st[7]},
         "library_sha256_16": kernel_hash(),
     }
     line.update(extras)
     print(json.dumps(line), flush=True)
+
+
+def roofline_of(st, kern_s, n_photons):
+    """Roofline of the transport kernel for one launch of n_photons photons
+    whose average duration kern_s was measured with HIP events on its stream.
+
+    The binding resource is VALU issue: the calibrated shader-sequencer
+    counters (committed summary) show a VALU instruction issuing in about 89 %
+    of the SIMD cycles, while the requests reaching L2 and the bytes leaving
+    it are about a fifth and a quarter of the streaming rates measured for
+    those levels.  `achieved` is the launch's algorithmic VALU work (per node
+    visit, triangle test and photon-step, times the counts of the counting
+    launch) per second against the VALU lane-operation peak; the executed
+    work, the lane activity and the memory levels come from the summaries
+    when they were taken on the current library."""
+    n_steps, n_nodes, n_tris = st[9], st[10], st[11]
+    ops = OPS_NODE * n_nodes + OPS_TRI * n_tris + OPS_STEP * n_steps
+    achieved = ops / kern_s
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_PEAK / 1e12,
+         "unit": "Tops/s", "frac": achieved / VALU_LANE_PEAK, "traffic": None,
+         "kernel": "propagate_kernel<forward>", "avg_launch_s": kern_s,
+         "algorithmic_lane_ops_per_launch": ops,
+         "lane_ops_per_unit": {"node_visit": OPS_NODE, "triangle_test": OPS_TRI,
+                               "photon_step": OPS_STEP}}
+    tr = profile_values(TRAFFIC_FILE, n_photons)
+    if tr:
+        r["traffic"] = tr["hbm_bytes_per_launch"] / kern_s / 1e9
+        r["traffic_unit"] = "GB/s"
+        r["traffic_bytes_per_launch"] = tr["hbm_bytes_per_launch"]
+    alg_bytes = NODE_BYTES * n_nodes + TRI_BYTES * n_tris
+    r["hbm_algorithmic"] = {
+        "achieved": alg_bytes / kern_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+        "frac": alg_bytes / kern_s / HBM_PEAK, "bytes_per_launch": alg_bytes,
+        "note": "128 B per node visit + 64 B per triangle test; above 1 because the 100 MB of "
+                "nodes and triangle records are read from L2 and the Infinity Cache, not HBM"}
+    v = profile_values(VALU_FILE, n_photons)
+    if v:
+        r["valu"] = {"issue_busy": v["valu_issue_busy"],
+                     "dual_issue_fraction": v["valu_dual_issue_fraction"],
+                     "active_lane_fraction": v["valu_active_lane_fraction"],
+                     "executed_lane_ops_per_photon_step": v["executed_lane_ops_per_photon_step"],
+                     "executed_over_algorithmic": v["executed_lane_ops_per_launch"] / ops}
+    l2, sp = profile_values(L2_FILE, n_photons), profile_values(STREAM_FILE)
+    if l2 and sp:
+        a2 = l2["l2_request_bytes_per_launch"] / kern_s / 1e9
+        a3 = l2["past_l2_read_bytes_per_launch"] / kern_s / 1e9
+        r["l2"] = {"achieved": a2, "peak": sp["l2_stream_read_GBps"], "unit": "GB/s",
+                   "frac": a2 / sp["l2_stream_read_GBps"], "peak_kind": "measured streaming read"}
+        r["past_l2"] = {"achieved": a3, "peak": sp["infinity_cache_stream_read_GBps"], "unit": "GB/s",
+                        "frac": a3 / sp["infinity_cache_stream_read_GBps"],
+                        "peak_kind": "measured streaming read from the Infinity Cache"}
+    return r
 
 
 def gradient_overhead(torch, W, Detector, dev):
@@ -366,44 +417,6 @@ def arrival_time_and_losses(torch, W, Detector, mesh, det, dev, n_photons):
         "absorbed_fraction_by_component": absorbed}}
 
 
-def design_variants(torch, W, Detector, dev, n=20_000_000):
-    """The paper's design variants on the same kernels: average LCE split into
-    {top, bottom, side} arrays, t90 (NR profile) and throughput, 2e7 photons
-    uniform in the active volume each."""
-    from paper_2203_14354_amd import runtime
-    out = {}
-    for name, kw in (("baseline", {}), ("coated_gate", dict(coating="gate")),
-                     ("coated_all", dict(coating="all")), ("single_phase", dict(single_phase=True)),
-                     ("no_bottom_array", dict(bottom_array=False)),
-                     ("4pi_pmt2_copper_fsr", dict(side_array="pmt2")),
-                     ("4pi_pmt2_coated_fsr", dict(side_array="pmt2", fsr="coated")),
-                     ("4pi_pmt2_no_fsr", dict(side_array="pmt2", fsr=None)),
-                     ("4pi_pmt2_copper_fsr_silicon_plates", dict(side_array="pmt2", plates="silicon")),
-                     ("4pi_sipm_copper_fsr", dict(side_array="sipm"))):
-        m = W.darwin(**kw)
-        t0 = time.perf_counter()
-        det = Detector(m, device=0, channel_of_sensor=W.darwin_array_channels(m), n_channels=3)
-        build = time.perf_counter() - t0
-        src = W.with_scintillation(W.darwin_tpc(n_photons=n, mesh=m).sources)
-        ds = det.sources(src)
-        hm = torch.zeros((1, 3), dtype=torch.int32, device=dev)
-        th = torch.zeros((1, 2048), dtype=torch.int32, device=dev)
-        run = lambda: det.propagate(ds, seed=7, hit_map=hm)
-        run()
-        d, _ = timed_launches(run, 2, torch)
-        hm.zero_()
-        det.propagate(ds, seed=7, hit_map=hm, time_hist=th, time_bin_ns=1.0)
-        lce = hm.cpu().numpy()[0].astype(np.float64) / n
-        out[name] = {"triangles": int(m.n_triangles), "sensors": int(m.n_sensors),
-                     "bvh_build_s": build, "photons_per_s": n / statistics.median(d),
-                     "lce": float(lce.sum()), "lce_top_bottom_side": [float(x) for x in lce],
-                     "t90_ns": float(runtime.time_quantile(th, 1.0, 0.9)[0])}
-        det.close()
-    return {"design_variants": {"workload": f"DARWIN-scale variants, {n} photons uniform in the "
-                                            "active volume each, NR scintillation profile",
-                                "variants": out}}
-
-
 def cache_probe(torch, dev):
     """Streaming-read bandwidth of buffers that fit the eight 4 MB L2 caches
     (16 MB: each XCD's workgroups touch one eighth), the 256 MB Infinity Cache
@@ -434,8 +447,10 @@ def cache_probe(torch, dev):
 
 
 # VALU instructions one iteration of the probe loop issues per wave (64
-# steps on eight chains; the integer step is an xor and an add)
-VALU_PROBE_KINDS = {0: ("fp32_fma", 64), 1: ("fp32_rcp", 64), 2: ("int32_xor_add", 128)}
+# steps on eight chains, one to three instructions per step by kind)
+VALU_PROBE_KINDS = {0: ("fp32_fma", 64), 1: ("fp32_rcp", 64), 2: ("int32_xor_add", 128),
+                    3: ("fp32_fma_and_int32_xor_add", 192), 4: ("fp32_fma_and_rcp", 128),
+                    5: ("u64_mad_and_move", 128)}
 
 
 def valu_probe(torch, dev, iters=20_000):
@@ -485,18 +500,49 @@ def spectrum_cost(torch, W, det, mesh, dev, n=20_000_000):
                          / out["gaussian_spectrum"]["photons_per_s"]}}
 
 
-def cpu_baseline(W, mesh, seed, sample):
-    """The FP64 oracle, as it stands, on the first `sample` photons of the same workload."""
+def cpu_baseline(W, mesh, seed, reps=3):
+    """The FP64 oracle as it stands (OpenMP over photons on the host threads
+    it is given, its own BVH for the closest hit), median of `reps` runs on
+    each of: the small-TPC workload in full (1e5 photons); photon ids
+    0 .. 1e6-1 of the DARWIN-scale workload (the GPU's first 1e6 photons);
+    the differentiable workload in full (1e7 photons, FP64 gradient
+    tallies).  `value` is the DARWIN-scale rate, the benchmark's workload."""
     import oracle
-    sc = oracle.Scene(mesh, use_bvh=True)
-    src = W.darwin_tpc(n_photons=sample, seed=seed, mesh=mesh).sources
     threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.run(sc, src, seed=seed, records=False, hit_map=True)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
-            "sample": f"photon ids 0..{sample - 1} of the DARWIN-scale workload "
-                      f"(FP64, OpenMP, {threads} threads), {dt:.1f} s"}
+
+    def median_rate(scene, src, **kw):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.run(scene, src, seed=seed, records=False, hit_map=True, **kw)
+            ts.append(time.perf_counter() - t0)
+        return src.n_photons / statistics.median(ts), ts
+
+    runs = {}
+    wl1 = W.small_tpc()
+    runs["small_tpc"] = median_rate(oracle.Scene(wl1.mesh, use_bvh=True), wl1.sources)
+    src2 = W.darwin_tpc(n_photons=1_000_000, seed=seed, mesh=mesh).sources
+    runs["darwin_tpc_first_1e6"] = median_rate(oracle.Scene(mesh, use_bvh=True), src2)
+    wl4 = W.differentiable(photons_per_point=1_000_000)
+    runs["differentiable"] = median_rate(oracle.Scene(wl4.mesh, use_bvh=True), wl4.sources,
+                                         grad=True)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    value = runs["darwin_tpc_first_1e6"][0]
+    return {"value": value, "unit": "photons/s", "cores": threads, "kind": "oracle",
+            "sample": f"photon ids 0..999999 of the DARWIN-scale workload, FP64, OpenMP on "
+                      f"{threads} threads, median of {reps} runs",
+            "per_core": value / threads, "cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "configs": {k: {"photons_per_s": r, "per_core": r / threads,
+                            "seconds": [round(t, 3) for t in ts]}
+                        for k, (r, ts) in runs.items()}}
 
 
 if __name__ == "__main__":
