@@ -402,6 +402,26 @@ int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params*
                     uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
                     xp_stream stream);
 
+/* xp_propagate for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launch and the same results, but the work counter and
+ * the traversal-stack overflow area live in a fixed 64 MiB device array that
+ * the library holds on every device it runs on until the process ends (its
+ * address is looked up once per device by xp_context_create).  The call
+ * allocates nothing; inputs and outputs are as in xp_propagate.  The overflow
+ * area needs 4 * max_stack bytes per lane (xp_bvh_info.max_stack) for every
+ * lane of the launch: with lc NULL or lc->blocks_per_cu 0 the call runs fewer
+ * workgroups per CU when the default would not fit (results do not depend on
+ * it); a launch that does not fit with the caller's blocks_per_cu, or with one
+ * workgroup per CU, fails with XP_ERR_UNSUPPORTED.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device (other
+ * streams, other contexts, other threads) race and give wrong results; the
+ * caller serializes them.  Errors: as xp_propagate, plus XP_ERR_UNSUPPORTED
+ * (scratch too small for the launch). */
+int xp_propagate_static(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                        int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                        uint64_t* d_stats, const xp_launch_cfg* lc, xp_stream stream);
+
 /* Loss group of every mesh triangle (host int32 [n_triangles], mesh order,
  * copied; values in [0, n_groups)), e.g. the detector component it belongs to.
  * Must follow xp_load_mesh.  Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG,

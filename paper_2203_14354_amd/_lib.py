@@ -109,7 +109,8 @@ assert RECORD_DTYPE.itemsize == 96
 EXPORTS = ["xp_context_create", "xp_context_destroy", "xp_last_error", "xp_load_mesh",
            "xp_set_materials", "xp_set_material_dispersion", "xp_set_surfaces",
            "xp_set_channel_map", "xp_build_bvh",
-           "xp_bvh_stats", "xp_propagate", "xp_propagate_ex", "xp_set_loss_groups",
+           "xp_bvh_stats", "xp_propagate", "xp_propagate_ex", "xp_propagate_static",
+           "xp_set_loss_groups",
            "xp_time_quantile", "xp_backward", "xp_autotune", "xp_closest_hit", "xp_sample",
            "xp_sample_emission_time", "xp_sample_wavelength", "xp_surface_reflectance",
            "xp_stream_read", "xp_valu_probe",
@@ -142,6 +143,7 @@ def load():
         "xp_bvh_stats": (ctypes.c_int, [P, P]),
         "xp_propagate": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
         "xp_propagate_ex": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P]),
+        "xp_propagate_static": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
         "xp_set_loss_groups": (ctypes.c_int, [P, P, I32]),
         "xp_time_quantile": (ctypes.c_int, [P, I64, I32, F, F, P, P]),
         "xp_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),

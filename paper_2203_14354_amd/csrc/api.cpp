@@ -372,8 +372,11 @@ void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_l
   a.n_time_cells = a.n_loss_cells = 0;
 }
 
+// fixed_counter: the work counter to use (the fixed scratch's), else one of
+// the context's
 int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records, bool count,
-           const xp_launch_cfg& lc, int grid, hipStream_t s) {
+           const xp_launch_cfg& lc, int grid, hipStream_t s,
+           unsigned long long* fixed_counter = nullptr) {
   if (a.n_photons == 0) return XP_OK;
   // A launch captured in a graph keeps its counter for every replay, so it
   // gets one that no other launch will use; eager launches reuse the ring.
@@ -381,7 +384,9 @@ int launch(xp_context* ctx, xp::LaunchArgs& a, int mode, bool grad, bool records
   hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
   unsigned long long* counter;
-  if (cap == hipStreamCaptureStatusActive) {
+  if (fixed_counter != nullptr) {
+    counter = fixed_counter;
+  } else if (cap == hipStreamCaptureStatusActive) {
     if (ctx->graph_next >= xp::kGraphCounters)
       return fail(ctx, XP_ERR_UNSUPPORTED, "more than " + std::to_string(xp::kGraphCounters) +
                                                " launches captured in graphs on this context");
@@ -425,6 +430,8 @@ int xp_context_create(int hip_device, xp_context** out) {
     ctx->device = hip_device;
     ctx->n_cu = prop.multiProcessorCount;
     ctx->max_lds = prop.sharedMemPerBlock;
+    e = xp::scratch_init(hip_device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
     e = hipMalloc(&ctx->d_counters,
                   (xp::kCounterRing + xp::kGraphCounters) * sizeof(unsigned long long));
     if (e != hipSuccess) {
@@ -769,11 +776,14 @@ int xp_bvh_stats(const xp_context* ctx, xp_bvh_info* out) {
 
 namespace {
 
-// Forward launch of xp_propagate_ex.
+// Forward launch of xp_propagate_ex (use_scratch false: the context's work
+// counters and stack overflow area) and of xp_propagate_static (true: the
+// fixed device scratch; no allocation, fewer workgroups per CU if the
+// overflow area would not fit it).
 int propagate_forward(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
                       int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
                       uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
-                      xp_stream stream) {
+                      xp_stream stream, bool use_scratch) {
   try {
     xp::LaunchArgs a;
     xp_launch_cfg cfg;
@@ -806,10 +816,31 @@ int propagate_forward(xp_context* ctx, const xp_sources* src, const xp_run_param
       a.tri_group = ctx->d_tri_group;
       a.n_groups = ctx->n_groups;
     }
+    unsigned long long* fixed_counter = nullptr;
+    if (use_scratch) {
+      char* base = static_cast<char*>(xp::scratch_base(ctx->device));
+      if (base == nullptr) return fail(ctx, XP_ERR_STATE, "device scratch not set up");
+      // the overflow area holds stack_total entries per lane of the launch
+      const size_t per_lane = size_t(a.stack_total) * sizeof(int32_t);
+      const size_t room = xp::kScratchBytes - xp::kScratchCounterBytes;
+      const bool caller_fixed = lc != nullptr && lc->blocks_per_cu > 0;
+      while (size_t(grid) * size_t(cfg.block_size) * per_lane > room) {
+        if (caller_fixed || cfg.blocks_per_cu <= 1)
+          return fail(ctx, XP_ERR_UNSUPPORTED,
+                      "the launch's traversal-stack overflow area needs " +
+                          std::to_string(size_t(grid) * size_t(cfg.block_size) * per_lane) +
+                          " bytes; the fixed scratch holds " + std::to_string(room) +
+                          " (fewer blocks_per_cu or a smaller block_size)");
+        cfg.blocks_per_cu -= 1;
+        grid = ctx->n_cu * cfg.blocks_per_cu;
+      }
+      fixed_counter = reinterpret_cast<unsigned long long*>(base);
+      a.stack_overflow = reinterpret_cast<int32_t*>(base + xp::kScratchCounterBytes);
+    }
     choose_block_tally(ctx, src, cfg, d_hit_map != nullptr, d_grad != nullptr, d_records != nullptr,
                        d_stats != nullptr, a);
     return launch(ctx, a, xp::kForward, d_grad != nullptr, d_records != nullptr, d_stats != nullptr,
-                  cfg, grid, static_cast<hipStream_t>(stream));
+                  cfg, grid, static_cast<hipStream_t>(stream), fixed_counter);
   } catch (...) {
     return fail(ctx, XP_ERR_HIP, "unexpected exception");
   }
@@ -823,7 +854,15 @@ int xp_propagate_ex(xp_context* ctx, const xp_sources* src, const xp_run_params*
                     int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
                     uint64_t* d_stats, const xp_extra_tallies* extra, const xp_launch_cfg* lc,
                     xp_stream stream) {
-  return propagate_forward(ctx, src, rp, d_hit_map, d_grad, d_records, d_stats, extra, lc, stream);
+  return propagate_forward(ctx, src, rp, d_hit_map, d_grad, d_records, d_stats, extra, lc, stream,
+                           false);
+}
+
+int xp_propagate_static(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
+                        int32_t* d_hit_map, double* d_grad, xp_photon_record* d_records,
+                        uint64_t* d_stats, const xp_launch_cfg* lc, xp_stream stream) {
+  return propagate_forward(ctx, src, rp, d_hit_map, d_grad, d_records, d_stats, nullptr, lc,
+                           stream, true);
 }
 
 int xp_propagate(xp_context* ctx, const xp_sources* src, const xp_run_params* rp, int32_t* d_hit_map,

@@ -2,9 +2,42 @@
 // variants without LDS tallies, and the small kernels behind the test hooks
 // (closest hit, emission sampling, reflectance, arrival-time quantiles,
 // streaming-read probe).  The transport itself is in transport.h.
+#include <mutex>
+
 #include "transport.h"
 
 namespace xp {
+
+// Scratch of xp_propagate_static, a file-scope device array that every device
+// the module runs on holds until the process ends, so that the entry point
+// needs no allocation.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol); it passes the device
+// address hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mutex;
+void* scratch_address[kScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (scratch_address[device] != nullptr) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (p == nullptr) return hipErrorInvalidSymbol;
+  scratch_address[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_base(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  return scratch_address[device];
+}
 
 namespace {
 

@@ -160,6 +160,16 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
                 const int32_t* mat_out, const int32_t* surface, const int32_t* sensor,
                 int max_leaf, int bins, double split_budget, BvhResult& out, std::string& err);
 
+// Fixed device scratch of the allocation-free entry point (defined in the
+// kernel translation unit): the work counter in its first 256 bytes, the
+// traversal-stack overflow area after it.  scratch_init (once per device,
+// with that device current) looks up the array's device address;
+// scratch_base returns it (nullptr before scratch_init on that device).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchCounterBytes = 256;
+hipError_t scratch_init(int device);
+void* scratch_base(int device);
+
 // Launch wrappers (defined in the kernel translation unit).
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
 hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool records, bool count,

@@ -217,6 +217,28 @@ class Detector:
         out["_keep"] = ds
         return out
 
+    def propagate_static(self, src, hit_map: torch.Tensor, seed=0, pid_base=0, max_steps=10_000,
+                         eps=0.0, grad_material=0, grad: Optional[torch.Tensor] = None,
+                         records: Optional[torch.Tensor] = None,
+                         stats: Optional[torch.Tensor] = None, launch: Optional[dict] = None,
+                         n_photons: Optional[int] = None, stream=None):
+        """xp_propagate_static: the forward launch with its work counter and
+        traversal-stack overflow area in the library's fixed device scratch.
+        Every output is the caller's tensor (hit map int32 [events, channels],
+        optional FP64 grad [events, channels, 4], uint8 records [n, 96], int64
+        stats [24]) and src should already be device sources (self.sources),
+        so that neither this call nor the library allocates."""
+        ds = self.sources(src)
+        n = ds.n_photons if n_photons is None else int(n_photons)
+        lc = launch_cfg(launch)
+        s = stream if stream is not None else current_stream(self.device)
+        sstruct = ds.struct(n)
+        rp = self.run_params(seed, pid_base, max_steps, eps, grad_material)
+        check(self.lib.xp_propagate_static(self.ctx, ctypes.byref(sstruct), ctypes.byref(rp),
+                                           _ptr(hit_map), _ptr(grad), _ptr(records), _ptr(stats),
+                                           ctypes.byref(lc) if lc else None, ctypes.c_void_p(s)),
+              self.ctx)
+
     def backward(self, src, grad_hits: torch.Tensor, seed=0, pid_base=0, max_steps=10_000,
                  eps=0.0, grad_material=0, grad_params: Optional[torch.Tensor] = None,
                  launch: Optional[dict] = None, stream=None) -> torch.Tensor:
