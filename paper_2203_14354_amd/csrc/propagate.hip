@@ -243,10 +243,10 @@ __global__ void sample_kernel(int32_t kind, uint32_t s0, uint32_t s1, uint64_t p
   out_pol[3 * i] = p.pol.x; out_pol[3 * i + 1] = p.pol.y; out_pol[3 * i + 2] = p.pol.z;
 }
 
-template <int kMode, bool kGrad, bool kRecords, bool kCount>
+template <int kMode, bool kGrad, bool kRecords, bool kCount, bool kOffsets = false>
 hipError_t launch_one(const LaunchArgs& a, int block, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((propagate_kernel<kMode, kGrad, kRecords, kCount>), dim3(grid), dim3(block),
-                     lds, s, a);
+  hipLaunchKernelGGL((propagate_kernel<kMode, kGrad, kRecords, kCount, kOffsets>), dim3(grid),
+                     dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -268,12 +268,19 @@ hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool recor
   const bool tally = mode == kForward && a.tally_bytes > 0 && !records && !count;
   const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block,
                                          tally ? size_t(a.tally_bytes) : 0);
+  // sources with prefix offsets: the variants with the wave-uniform source
+  // cursor (records and counters keep the per-photon search; same results)
+  const bool offs = a.src_kind == XP_SRC_POINTS && a.offsets != nullptr;
   if (mode == kBackward) {
     if (records || count || grad) return hipErrorInvalidValue;
-    return launch_one<kBackward, false, false, false>(a, block, grid, lds, s);
+    return offs ? launch_one<kBackward, false, false, false, true>(a, block, grid, lds, s)
+                : launch_one<kBackward, false, false, false>(a, block, grid, lds, s);
   }
   if (mode != kForward) return hipErrorInvalidValue;
-  if (tally) return launch_propagate_tally(a, grad, block, grid, lds, s);
+  if (tally) return launch_propagate_tally(a, grad, offs, block, grid, lds, s);
+  if (offs && !records && !count)
+    return grad ? launch_one<kForward, true, false, false, true>(a, block, grid, lds, s)
+                : launch_one<kForward, false, false, false, true>(a, block, grid, lds, s);
   const int key = (grad ? 4 : 0) | (records ? 2 : 0) | (count ? 1 : 0);
   switch (key) {
     case 0: return launch_one<kForward, false, false, false>(a, block, grid, lds, s);
@@ -291,11 +298,11 @@ hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, bool tally
   if (tally) return max_blocks_per_cu_tally(block, lds_bytes, out);
   if (count)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        out, reinterpret_cast<const void*>(propagate_kernel<kForward, true, true, true>), block,
-        lds_bytes);
+        out, reinterpret_cast<const void*>(propagate_kernel<kForward, true, true, true, false>),
+        block, lds_bytes);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      out, reinterpret_cast<const void*>(propagate_kernel<kForward, false, false, false>), block,
-      lds_bytes);
+      out, reinterpret_cast<const void*>(propagate_kernel<kForward, false, false, false, false>),
+      block, lds_bytes);
 }
 
 hipError_t launch_emission_time(uint64_t seed, uint64_t pid0, int64_t n, float tau_singlet,

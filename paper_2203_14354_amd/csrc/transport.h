@@ -658,6 +658,24 @@ __device__ __forceinline__ int64_t source_of(const LaunchArgs& a, int64_t i) {
   return lo;
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// Source of photon i for sources with prefix offsets, with i the same in every
+// lane of the wave: one search for the wave, each load at one address.
+__device__ __forceinline__ int64_t wave_source_of(const LaunchArgs& a, int64_t i) {
+  i = uniform64(i);
+  int64_t lo = 0, hi = uniform64(a.n_sources);
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (uniform64(a.offsets[mid]) <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Emission time from the two-component scintillation decay: Philox block
 // (step 0, sub 2), u0 picks the singlet state with its fraction, u1 the decay.
 __device__ __forceinline__ float emission_time(uint32_t s0, uint32_t s1, uint64_t pid,
@@ -688,7 +706,10 @@ __device__ __forceinline__ f3 cylinder_point(uint32_t s0, uint32_t s1, uint64_t 
   return {rr * cp, rr * sp, zlo + (zhi - zlo) * q.u2};
 }
 
-__device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid) {
+// Emit photon i (launch-local) with id pid; src, when >= 0, is its source
+// (POINTS), already known to the caller.
+__device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, uint64_t pid,
+                                     int64_t src = -1) {
   p.time = 0.0f;
   p.wavelength = emission_wavelength(a.seed_lo, a.seed_hi, pid, a.wl_mean, a.wl_sigma);
   if (a.time_profile == XP_TIME_SCINTILLATION) {
@@ -717,7 +738,7 @@ __device__ __forceinline__ void emit(Photon& p, const LaunchArgs& a, int64_t i, 
   p.dir = isotropic(r.u0, r.u1);
   p.pol = random_polarization(p.dir, r.u2);
   if (a.src_kind == XP_SRC_POINTS) {
-    const int64_t s = source_of(a, i);
+    const int64_t s = src >= 0 ? src : source_of(a, i);
     p.pos = {a.positions[3 * s], a.positions[3 * s + 1], a.positions[3 * s + 2]};
     p.event = a.per_source_events ? int32_t(s) : 0;
   } else {
@@ -920,7 +941,11 @@ enum : int32_t { kEmpty = 0, kTraversing = 1, kWaiting = 2 };
 // than the extra latency hiding gains.
 constexpr int kRefillMin = 4;  // empty lanes before a wave refills them
 
-template <int kMode, bool kGrad, bool kRecords, bool kCount>
+// kOffsets: the launch's sources are POINTS with prefix offsets; the refill
+// then finds the sources of the ids it hands out with a wave-uniform cursor
+// (one scalar binary search per chunk of ids, then a walk over the few
+// sources the chunk spans) instead of a binary search per photon.
+template <int kMode, bool kGrad, bool kRecords, bool kCount, bool kOffsets>
 __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   extern __shared__ float4 lds[];
   constexpr bool kGradAcc = kGrad || kMode == kBackward;
@@ -958,6 +983,9 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   int64_t idx = 0;
   uint64_t pid = 0;
   uint64_t pool_next = 0, pool_end = 0;
+  // kOffsets: a source at or before that of photon pool_next, and the first
+  // photon of the source after it (the largest int64 if there is none)
+  int64_t cur_src = 0, cur_next = 0;
   bool exhausted = false;
   Counters cnt{0u, 0u, 0u, 0u};
   uint32_t n_steps = 0;
@@ -1083,18 +1111,41 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
           }
           pool_next = base;
           pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
+          if (kOffsets) {
+            cur_src = wave_source_of(a, int64_t(base));
+            cur_next = cur_src + 1 < a.n_sources ? uniform64(a.offsets[cur_src + 1]) : INT64_MAX;
+          }
         }
         const uint64_t avail = pool_end - pool_next;
         const uint32_t rank = lane_rank(dead);
+        const uint64_t ndead = uint64_t(__popcll(dead));
+        const uint64_t ntake = ndead < avail ? ndead : avail;
+        int64_t src = -1;
+        if (kOffsets) {
+          // sources of ids pool_next .. last: walk the offsets forward from the
+          // cursor (wave-uniform loads); each lane keeps the last source that
+          // starts at or before its id, as the binary search would find
+          const int64_t mine = int64_t(pool_next) + int64_t(rank);
+          const int64_t last = uniform64(int64_t(pool_next + ntake) - 1);
+          const int64_t n_src = uniform64(a.n_sources);
+          int64_t s = uniform64(cur_src), next_start = uniform64(cur_next);
+          src = s;
+          while (next_start <= last) {  // ids up to `last` reach source s + 1
+            ++s;
+            if (mine >= next_start) src = s;
+            next_start = s + 1 < n_src ? uniform64(a.offsets[s + 1]) : INT64_MAX;
+          }
+          cur_src = s;
+          cur_next = next_start;
+        }
         if (state == kEmpty && rank < avail) {
           idx = int64_t(pool_next + rank);
           pid = a.pid_base + uint64_t(idx);
           state = kTraversing;
           start = true;
-          emit(p, a, idx, pid);
+          emit(p, a, idx, pid, src);
         }
-        const uint64_t ndead = uint64_t(__popcll(dead));
-        pool_next += ndead < avail ? ndead : avail;
+        pool_next += ntake;
         dead = __ballot(state == kEmpty);
       }
       if (__ballot(state != kEmpty) == 0ull) break;  // pool exhausted and every lane idle

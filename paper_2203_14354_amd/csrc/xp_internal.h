@@ -176,8 +176,8 @@ hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool recor
                             int block, int grid, hipStream_t s);
 hipError_t max_blocks_per_cu(int block, size_t lds_bytes, bool count, bool tally, int* out);
 // the kForwardTally variants (compiled apart, in propagate_tally.hip)
-hipError_t launch_propagate_tally(const LaunchArgs& a, bool grad, int block, int grid, size_t lds,
-                                  hipStream_t s);
+hipError_t launch_propagate_tally(const LaunchArgs& a, bool grad, bool offsets, int block,
+                                  int grid, size_t lds, hipStream_t s);
 hipError_t max_blocks_per_cu_tally(int block, size_t lds_bytes, int* out);
 // LDS bytes of the per-workgroup tallies (a multiple of 16)
 __host__ __device__ inline size_t tally_lds_bytes(int32_t cells, bool grad) {
