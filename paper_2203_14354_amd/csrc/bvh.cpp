@@ -70,14 +70,24 @@ float round_up(double x) {
 }
 
 struct Poly {
+  static constexpr int kCap = 3 + 2 * 6;
   int n = 0;
-  double v[3 + 2 * 6][3];  // a triangle clipped by at most six planes
+  bool overflow = false;  // a clip would have exceeded kCap vertices
+  double v[kCap][3];      // a triangle clipped by at most six planes (one vertex each)
 };
 
 // Clip a convex polygon to {x[axis] <= c} (keep_below) or {x[axis] >= c}.
+// Each plane adds at most one vertex to a convex polygon; should rounding make
+// an edge list cross the plane more often, the result is marked as overflowed
+// rather than written past its capacity.
 Poly clip(const Poly& in, int axis, double c, bool keep_below) {
   Poly out;
+  out.overflow = in.overflow;
   for (int i = 0; i < in.n; ++i) {
+    if (out.n + 2 > Poly::kCap) {
+      out.overflow = true;
+      return out;
+    }
     const double* p = in.v[i];
     const double* q = in.v[(i + 1) % in.n];
     const double dp = keep_below ? c - p[axis] : p[axis] - c;
@@ -109,9 +119,23 @@ bool make_piece(const double tri[3][3], const double n_l1, Piece& pc) {
   poly.n = 3;
   for (int j = 0; j < 3; ++j)
     for (int k = 0; k < 3; ++k) poly.v[j][k] = tri[j][k];
-  for (int k = 0; k < 3 && poly.n > 0; ++k) {
+  for (int k = 0; k < 3 && poly.n > 0 && !poly.overflow; ++k) {
     if (std::isfinite(pc.cell_lo[k])) poly = clip(poly, k, pc.cell_lo[k], false);
     if (poly.n > 0 && std::isfinite(pc.cell_hi[k])) poly = clip(poly, k, pc.cell_hi[k], true);
+  }
+  if (poly.overflow) {
+    // conservative piece: the triangle's box within the cell, never split further
+    for (int k = 0; k < 3; ++k) {
+      double lo = std::min(std::min(tri[0][k], tri[1][k]), tri[2][k]);
+      double hi = std::max(std::max(tri[0][k], tri[1][k]), tri[2][k]);
+      if (std::isfinite(pc.cell_lo[k])) lo = std::max(lo, pc.cell_lo[k]);
+      if (std::isfinite(pc.cell_hi[k])) hi = std::min(hi, pc.cell_hi[k]);
+      if (lo > hi) return false;
+      pc.lo[k] = round_down(lo);
+      pc.hi[k] = round_up(hi);
+    }
+    pc.waste = 0.0;
+    return true;
   }
   if (poly.n < 3) return false;
   double lo[3], hi[3];
