@@ -64,7 +64,7 @@ def profile_values(path: str, photons_per_launch=None):
     if not os.path.exists(path):
         return None
     vals = {}
-    for m in re.finditer(r"^([a-z0-9_]+):\s*([0-9a-f.eE+-]+)\s*$", open(path).read(), re.M):
+    for m in re.finditer(r"^([A-Za-z0-9_]+):\s*([0-9a-f.eE+-]+)\s*$", open(path).read(), re.M):
         vals[m.group(1)] = m.group(2)
     if photons_per_launch is not None:
         if vals.get("library_sha256_16") != kernel_hash():
