@@ -495,22 +495,9 @@ struct LaneStack {
   }
 };
 
-// compare-exchange of (key, value) pairs: ascending keys
-__device__ __forceinline__ void cswap(float& ka, int32_t& va, float& kb, int32_t& vb) {
-  const bool sw = kb < ka;
-  const float k = sw ? kb : ka;
-  const int32_t v = sw ? vb : va;
-  kb = sw ? ka : kb;
-  vb = sw ? va : vb;
-  ka = k;
-  va = v;
-}
-
-// Visit one inner node: test its four child boxes, bring the nearest hit to
-// the front, then follow one inner child and hold one leaf (for the kind of
-// the nearest hit, that hit; for the other kind the first in node order; a
-// leaf the lane still holds is pushed) and push the other hits.  Stack
-// entries are node indices (>= 0) or complemented packed leaves
+// Visit one inner node: test its four child boxes, follow the nearest hit if
+// it is an inner node or hold it if it is a leaf, and push the other hits.
+// Stack entries are node indices (>= 0) or complemented packed leaves
 // (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
 template <bool kCount>
 __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
@@ -531,8 +518,11 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   const float hiz[4] = {q[5].x, q[5].y, q[5].z, q[5].w};
   const int32_t child[4] = {__float_as_int(q[6].x), __float_as_int(q[6].y),
                             __float_as_int(q[6].z), __float_as_int(q[6].w)};
-  float key[4];
-  int32_t ent[4];
+  // Each hit child's entry distance (>= 0, so its bits order as the value
+  // does) with the child's slot in the two low bits; a miss is all ones.  The
+  // smallest key is the nearest hit (ties, and distances within 4 ulp, go to
+  // the lower slot), found with two integer minima instead of sorting.
+  uint32_t key[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float t0x = fmaf(lox[i], inv.x, -oi.x), t1x = fmaf(hix[i], inv.x, -oi.x);
@@ -543,38 +533,33 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
     // empty slots hold an inverted box (lo = +inf, hi = -inf), which every
     // slab test misses: no separate check of the child entry
     const bool hit = tn <= tf * 1.0000005f;
-    key[i] = hit ? tn : kInfF;
-    ent[i] = child[i];
+    key[i] = hit ? ((__float_as_uint(tn) & ~3u) | uint32_t(i)) : ~0u;
   }
-  // one exchange pass brings the nearest hit to slot 0 (misses carry an
-  // infinite key); the others keep their node order.  A full sort (five
-  // exchanges) pops the pushed children in a slightly better order but costs
-  // more than the few extra visits it saves.
-  cswap(key[2], ent[2], key[3], ent[3]);
-  cswap(key[1], ent[1], key[2], ent[2]);
-  cswap(key[0], ent[0], key[1], ent[1]);
-  constexpr int32_t kNone = -1 - 0x7fffffff;  // no entry (leaf entries stay above it)
-  // the held leaf and the followed node as stack entries, so that a spill is
-  // the entry itself (no conversions per child)
-  int32_t held_leaf = leaf >= 0 ? ~leaf : kNone;
-  int32_t next_node = kNone;
+  const uint32_t nearest = min(min(key[0], key[1]), min(key[2], key[3]));
+  const uint32_t j = nearest & 3u;
+  // every other hit is pushed (the lower slots on top); the nearest is
+  // followed if it is an inner node and held if it is a leaf.  Writes go to
+  // the slot above the top whether or not they count, so no branches.
   st.reserve4();
   int32_t npush = 0;
+  int32_t near_entry = child[3];
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
-    const int32_t e = ent[i];
-    const bool hit = key[i] != kInfF;
-    // the later leaf keeps the leaf slot, the later inner node is followed;
-    // the previous holder spills (selects only: branches here cost more)
-    const bool is_leaf = e < 0;
-    const int32_t spill = hit ? (is_leaf ? held_leaf : next_node) : kNone;
-    held_leaf = hit && is_leaf ? e : held_leaf;
-    next_node = hit && !is_leaf ? e : next_node;
-    st.put(npush, spill);  // a slot above the top: harmless when nothing spills
-    npush += spill != kNone ? 1 : 0;
+    const bool is_nearest = j == uint32_t(i);
+    near_entry = is_nearest ? child[i] : near_entry;
+    st.put(npush, child[i]);
+    npush += (key[i] != ~0u) & !is_nearest ? 1 : 0;
   }
-  node = max(next_node, -1);
-  leaf = held_leaf != kNone ? ~held_leaf : -1;
+  const bool any = nearest != ~0u;
+  const bool near_leaf = any & (near_entry < 0);
+  // a nearest leaf while the lane still holds one (leaves of several
+  // triangles): the held leaf goes to the stack
+  if (near_leaf & (leaf >= 0)) {
+    st.put(npush, ~leaf);
+    ++npush;
+  }
+  node = any & (near_entry >= 0) ? near_entry : -1;
+  leaf = near_leaf ? ~near_entry : leaf;
   if (st.sp + npush > st.total) return false;
   st.sp += npush;
   return true;

@@ -6,10 +6,10 @@ reference splitting cut long triangles into pieces), the leaf ranges and the
 three rotated record copies are consistent, and the host's worst-case stack
 bound covers the traversal the kernel runs.  These tests check each on meshes
 with long fan wedges (the shape the splitting targets): the first two
-directly, the last by running the kernel's traversal order (one exchange
-pass brings the nearest child hit to the front, one inner child is followed
-and one leaf held, the rest pushed) in Python over random rays, and comparing its closest hits with a
-brute-force FP64 intersection of every triangle.
+directly, the last by running the kernel's traversal order (the nearest child hit is
+followed, or held if it is a leaf, and the other hits are pushed) in Python
+over random rays, and comparing its closest hits with a brute-force FP64
+intersection of every triangle.
 """
 import numpy as np
 import pytest
@@ -208,26 +208,16 @@ def traverse(nodes, recs, n_refs, v, t, o, d):
         key = [tn[k] if nd["child"][k] != _lib.EMPTY_CHILD and tn[k] <= tf[k] else np.inf
                for k in range(4)]
         ent = [int(nd["child"][k]) for k in range(4)]
-        for a in (2, 1, 0):  # one exchange pass: the nearest hit to slot 0
-            if key[a + 1] < key[a]:
-                key[a], key[a + 1] = key[a + 1], key[a]
-                ent[a], ent[a + 1] = ent[a + 1], ent[a]
-        hits = [(key[k], ent[k]) for k in range(4) if key[k] != np.inf]
+        # the nearest hit (ties to the lower slot) is followed, or held if it is
+        # a leaf; every other hit is pushed, slot 3 first
+        j = int(np.argmin(key)) if min(key) != np.inf else -1
         node = None
-        held = None
-        pushes = []
-        for _, e in reversed(hits):  # slots 3..0: the later one keeps the slot
-            if e < 0:
-                if held is not None:
-                    pushes.append(held)
-                held = e
+        stack.extend(ent[k] for k in (3, 2, 1, 0) if k != j and key[k] != np.inf)
+        if j >= 0:
+            if ent[j] < 0:
+                leaf = ((~ent[j]) >> 3, ((~ent[j]) & 7) + 1)
             else:
-                if node is not None:
-                    pushes.append(node)
-                node = e
-        stack.extend(pushes)
-        if held is not None:
-            leaf = ((~held) >> 3, ((~held) & 7) + 1)
+                node = ent[j]
         max_depth = max(max_depth, len(stack) + (1 if leaf is not None else 0))
     return best_tri, max_depth
 
