@@ -310,8 +310,9 @@ typedef struct xp_launch_cfg {
                               or three where the fourth would lower the occupancy or
                               leave the launch's LDS tallies (block_tally) no room */
   int32_t stack_lds;       /* traversal-stack entries per lane kept in LDS, a power of
-                              two in 4..64 (0 = default 16); deeper entries spill to a
-                              global overflow area allocated by xp_build_bvh */
+                              two in 4..64 (0 = default 16); when a node visit would
+                              leave fewer than four of them free, the lane's LDS entries
+                              move to a global overflow area allocated by xp_build_bvh */
   int32_t wave_batch;      /* photons per wave interaction phase: a wave interrupts its
                               closest-hit searches to run the interactions, tallies and
                               refills once at least this many of its 64 lanes are not

@@ -1070,7 +1070,7 @@ int xp_autotune(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
         best = cand;
       }
     };
-    // stage 1: block size, staged BVH levels, LDS stack ring, interaction batch
+    // stage 1: block size, staged BVH levels, LDS stack window, interaction batch
     for (int b : {64, 256})
       for (int l : {0, -1})
         for (int sl : {8, 16})

@@ -51,11 +51,11 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
                                                          float tmin, float tmax, int32_t brute,
                                                          int32_t* out_tri, float* out_t) {
   extern __shared__ float4 lds[];
-  // the whole worst-case stack in LDS: stack_depth is a power of two of at
-  // least the bound plus the four slots a visit reserves; with the usable
-  // depth capped at stack_depth - 4 the ring never spills (no overflow array)
-  LaneStack stack{reinterpret_cast<int32_t*>(lds) + threadIdx.x, int32_t(blockDim.x),
-                  stack_depth - 1, nullptr, 0, stack_depth - 4, 0, 0};
+  // the whole worst-case stack in LDS: stack_depth is at least the bound
+  // plus the four slots a visit reserves; with the usable depth capped at
+  // stack_depth - 4 the window never spills (no overflow array)
+  lds_i32* const bottom = (lds_i32*)(reinterpret_cast<int32_t*>(lds)) + threadIdx.x;  // one wave per block
+  LaneStack stack{bottom, bottom, 64 * (stack_depth - 4), nullptr, 0, stack_depth - 4, 0};
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const f3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};

@@ -457,41 +457,49 @@ __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, con
   }
 }
 
-// Per-lane traversal stack: the newest `lds_cap` entries (a power of two, at
-// least 4) in an LDS ring, older ones spilled to this lane's column of a
-// global overflow array.  A node visit first makes room for its (at most four)
-// pushes, then writes them without further tests.  `total` is the
-// host-computed worst case; a visit that would exceed it fails.
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+
+// Per-lane traversal stack: the newest entries in a window of LDS slots (slot
+// k of a lane at bottom + 64 k, the 64 lanes of a wave side by side), the
+// older ones in this lane's column of a global overflow array.  A node visit
+// first makes room for its (at most four) pushes: if the window holds more
+// than `limit` entries, all of them move to the overflow array (rare: the
+// stack is seldom deeper than a few entries); pops read the overflow array
+// while the window is empty.  Pushes and pops move one LDS address.  `total`
+// is the host-computed worst case; a visit that would exceed it fails.
 struct LaneStack {
-  int32_t* lds;        // this lane's first LDS slot; slot k at lds[k * stride]
-  int32_t stride;
-  int32_t mask;        // lds_cap - 1
-  int32_t* glob;       // this lane's first overflow slot; slot k at glob[k * gstride]
+  lds_i32* bottom;     // this lane's window slot 0
+  lds_i32* top;        // the first free window slot
+  int32_t limit;       // 64 * (window slots - 4)
+  int32_t* glob;       // this lane's overflow column: entry k at glob[k * gstride]
   int64_t gstride;
   int32_t total;
-  int32_t sp, base;    // entries in use; entries held in the overflow array
-  // make room for four entries in the ring (the oldest move to the overflow array)
+  int32_t sp;          // entries in use, window and overflow
+  __device__ __forceinline__ void clear() {
+    sp = 0;
+    top = bottom;
+  }
+  // make room for four entries in the window
   __device__ __forceinline__ void reserve4() {
-    while (sp - base > mask - 3) {
-      glob[int64_t(base) * gstride] = lds[__mul24(base & mask, stride)];
-      ++base;
+    const int32_t held = int32_t(top - bottom);
+    if (held > limit) {
+      const int32_t first = sp - (held >> 6);  // stack index of window slot 0
+      for (int32_t k = 0; k < held; k += 64) glob[int64_t(first + (k >> 6)) * gstride] = bottom[k];
+      top = bottom;
     }
   }
   // write entry j (< 4) above the top; valid after reserve4
-  __device__ __forceinline__ void put(int32_t j, int32_t e) {
-    lds[__mul24((sp + j) & mask, stride)] = e;
+  __device__ __forceinline__ void put(int32_t j, int32_t e) { top[j * 64] = e; }
+  // the n entries written above the top join the stack
+  __device__ __forceinline__ void advance(int32_t n) {
+    top += n * 64;
+    sp += n;
   }
   __device__ __forceinline__ int32_t pop() {
     --sp;
-    if (sp < base) {
-      base = sp;
-      return glob[int64_t(sp) * gstride];
-    }
-    // read through an LDS-qualified pointer: with a generic one the compiler
-    // merges this read and the overflow read into one flat load through a
-    // selected address, which then waits for every outstanding memory access
-    typedef __attribute__((address_space(3))) const int32_t lds_int;
-    return *(lds_int*)(lds + __mul24(sp & mask, stride));
+    if (top == bottom) return glob[int64_t(sp) * gstride];
+    top -= 64;
+    return *top;
   }
 };
 
@@ -561,7 +569,7 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
   node = any & (near_entry >= 0) ? near_entry : -1;
   leaf = near_leaf ? ~near_entry : leaf;
   if (st.sp + npush > st.total) return false;
-  st.sp += npush;
+  st.advance(npush);
   return true;
 }
 
@@ -590,8 +598,7 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
   int32_t node = 0;   // inner node to visit next, or -1
   int32_t leaf = -1;  // postponed leaf (packed), or -1
   bool ok = true;
-  st.sp = 0;
-  st.base = 0;
+  st.clear();
   while (true) {
     // ---- node phase ----
     while (true) {
@@ -610,7 +617,7 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
             ok = false;
             node = -1;
             leaf = -1;
-            st.sp = 0;
+            st.clear();
           }
         }
       }
@@ -958,8 +965,10 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
       reinterpret_cast<int32_t*>(tally)[i] = 0;
   __syncthreads();
   const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  LaneStack stack{stack_base + threadIdx.x, int32_t(blockDim.x), a.stack_lds - 1,
-                  a.stack_overflow + gtid, int64_t(gridDim.x) * blockDim.x, a.stack_total, 0, 0};
+  lds_i32* const stack_bottom = (lds_i32*)(stack_base) +
+                                (threadIdx.x >> 6) * (a.stack_lds * 64) + (threadIdx.x & 63);
+  LaneStack stack{stack_bottom, stack_bottom, 64 * (a.stack_lds - 4), a.stack_overflow + gtid,
+                  int64_t(gridDim.x) * blockDim.x, a.stack_total, 0};
   const uint32_t lane = lane_rank(~0ull);
   const uint32_t batch_trigger = 64u - uint32_t(a.wave_batch);  // run the phase at <= this
 
@@ -1146,8 +1155,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         oi = f3{p.pos.x * inv.x, p.pos.y * inv.y, p.pos.z * inv.z};
         node = 0;
         leaf = -1;
-        stack.sp = 0;
-        stack.base = 0;
+        stack.clear();
         if (kCount) n_steps++;
       }
     }

@@ -17,7 +17,7 @@ constexpr int kMaxSurfaces = 16;
 constexpr int kCounterRing = 64;      // work counters of eager launches, reused in turn
 constexpr int kGraphCounters = 256;   // work counters of launches captured in graphs
 constexpr int kStatsWords = 24;
-constexpr int kStackLds = 16;        // LDS ring entries per lane
+constexpr int kStackLds = 16;        // LDS window entries per lane
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
 constexpr double kDefaultSplitBudget = 0.02;  // extra BVH references from pre-splitting
@@ -90,7 +90,7 @@ struct LaunchArgs {
   const int32_t* channel_of_sensor;
   int32_t n_tris;          // triangle references (records per rotated copy)
   int32_t n_lds_nodes;
-  int32_t stack_lds;       // LDS ring entries per lane (power of two)
+  int32_t stack_lds;       // LDS window entries per lane (power of two)
   int32_t stack_total;     // worst-case stack entries of the BVH
   int32_t* stack_overflow; // [stack_total][grid * block] spill slots
   int32_t n_channels;
