@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
   // plus the four slots a visit reserves; with the usable depth capped at
   // stack_depth - 4 the window never spills (no overflow array)
   lds_i32* const bottom = (lds_i32*)(reinterpret_cast<int32_t*>(lds)) + threadIdx.x;  // one wave per block
-  LaneStack stack{bottom, bottom, 64 * (stack_depth - 4), nullptr, 0, stack_depth - 4, 0};
+  LaneStack stack{bottom, bottom, 256 * (stack_depth - 4), nullptr, 0, stack_depth - 4, 0};
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const f3 o{orig[3 * i], orig[3 * i + 1], orig[3 * i + 2]};
@@ -68,9 +68,8 @@ __global__ void __launch_bounds__(64) closest_hit_kernel(const Node4* nodes, con
     const RayW r = make_ray(o, d, n_tris);
     for (int32_t k = 0; k < n_tris; ++k) test_triangle(tris, k, r, tmin, sk, b);
   } else {
-    // no node is staged (n_lds = 0); the LDS base is passed rather than a null
-    // pointer, which this toolchain's inliner fails on
-    ok = traverse<false>(nodes, lds, 0, tris, n_tris, stack, o, d, tmin, sk, b, c);
+    // no node is staged in LDS (n_lds = 0): the LDS holds the stack windows
+    ok = traverse<false>(nodes, 0, tris, n_tris, stack, o, d, tmin, sk, b, c);
   }
   out_tri[i] = ok ? b.tri : -2;
   out_t[i] = b.tri >= 0 ? b.t : kInfF;

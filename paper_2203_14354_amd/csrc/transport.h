@@ -435,25 +435,36 @@ struct Counters {
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
-// from LDS, the rest from global memory.  The box planes are fetched in the
-// order the ray meets them (near before far on each axis, by the signs of its
-// direction), so the slab test needs no per-axis min / max: with a
-// non-negative reciprocal the lower plane's entry distance is the smaller one
-// (rounding is monotone), and the reciprocals are never zero.
-__device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                           int32_t n_lds, int32_t node, int32_t sx, int32_t sy,
-                                           int32_t sz, float4 (&q)[7]) {
-  // q[0..5] = near x, far x, near y, far y, near z, far z (by the ray's signs)
-  const int32_t idx[6] = {sx, 1 - sx, 2 + sy, 3 - sy, 4 + sz, 5 - sz};
+// from LDS, where they start at address 0, the rest from global memory.  The
+// box planes are fetched in the order the ray meets them (near before far on
+// each axis, by the signs of its direction), so the slab test needs no
+// per-axis min / max: with a non-negative reciprocal the lower plane's entry
+// distance is the smaller one (rounding is monotone), and the reciprocals are
+// never zero.  Both paths read the node at the same byte offsets: a node is
+// 128 bytes, each axis's lower and upper planes 16 bytes apart in a 32-byte
+// pair, so the near plane is at (node << 7) | 16 * sign and the far plane at
+// that offset ^ 16.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f4v lds_f4;
+__device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, int32_t n_lds,
+                                           int32_t node, f3 inv, float4 (&q)[7]) {
+  const uint32_t base = uint32_t(node) << 7;
+  const uint32_t xn = base | ((__float_as_uint(inv.x) >> 31) << 4);
+  const uint32_t yn = base | ((__float_as_uint(inv.y) >> 31) << 4);
+  const uint32_t zn = base | ((__float_as_uint(inv.z) >> 31) << 4);
+  // q[0..5] = near x, far x, near y, far y, near z, far z; q[6] = children
+  const uint32_t off[7] = {xn, xn ^ 16u, yn + 32u, (yn ^ 16u) + 32u, zn + 64u, (zn ^ 16u) + 64u,
+                           base + 96u};
   if (node < n_lds) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) q[i] = lds_nodes[node * 8 + idx[i]];
-    q[6] = lds_nodes[node * 8 + 6];
+    for (int i = 0; i < 7; ++i) {
+      const f4v v = *(lds_f4*)(uintptr_t)off[i];
+      q[i] = make_float4(v.x, v.y, v.z, v.w);
+    }
   } else {
-    const float4* g = reinterpret_cast<const float4*>(gnodes + node);
+    const char* g = reinterpret_cast<const char*>(gnodes);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) q[i] = g[idx[i]];
-    q[6] = g[6];
+    for (int i = 0; i < 7; ++i) q[i] = *reinterpret_cast<const float4*>(g + off[i]);
   }
 }
 
@@ -470,7 +481,7 @@ typedef __attribute__((address_space(3))) int32_t lds_i32;
 struct LaneStack {
   lds_i32* bottom;     // this lane's window slot 0
   lds_i32* top;        // the first free window slot
-  int32_t limit;       // 64 * (window slots - 4)
+  int32_t limit;       // 256 * (window slots - 4): bytes of entries that leave four slots free
   int32_t* glob;       // this lane's overflow column: entry k at glob[k * gstride]
   int64_t gstride;
   int32_t total;
@@ -481,10 +492,11 @@ struct LaneStack {
   }
   // make room for four entries in the window
   __device__ __forceinline__ void reserve4() {
-    const int32_t held = int32_t(top - bottom);
+    // bytes between the 32-bit LDS addresses: 256 per entry
+    const int32_t held = int32_t((uint32_t)(uintptr_t)top - (uint32_t)(uintptr_t)bottom);
     if (held > limit) {
-      const int32_t first = sp - (held >> 6);  // stack index of window slot 0
-      for (int32_t k = 0; k < held; k += 64) glob[int64_t(first + (k >> 6)) * gstride] = bottom[k];
+      const int32_t first = sp - (held >> 8);  // stack index of window slot 0
+      for (int32_t k = 0; k < (held >> 8); ++k) glob[int64_t(first + k) * gstride] = bottom[64 * k];
       top = bottom;
     }
   }
@@ -508,15 +520,12 @@ struct LaneStack {
 // Stack entries are node indices (>= 0) or complemented packed leaves
 // (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
 template <bool kCount>
-__device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
-                                           const float4* lds_nodes, int32_t n_lds, f3 inv, f3 oi,
+__device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes, int32_t n_lds,
+                                           f3 inv, f3 oi,
                                            float tmax, LaneStack& st, int32_t& node,
                                            int32_t& leaf, Counters& cnt) {
   float4 q[7];
-  const int32_t sx = int32_t(uint32_t(__float_as_int(inv.x)) >> 31);
-  const int32_t sy = int32_t(uint32_t(__float_as_int(inv.y)) >> 31);
-  const int32_t sz = int32_t(uint32_t(__float_as_int(inv.z)) >> 31);
-  fetch_node(gnodes, lds_nodes, n_lds, node, sx, sy, sz, q);
+  fetch_node(gnodes, n_lds, node, inv, q);
   if (kCount) cnt.nodes++;
   const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};  // near planes
   const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};  // far planes
@@ -585,8 +594,8 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes,
 // triangle tests) instead of paying for both in every iteration.
 // Returns false only if the stack would overflow its host-computed bound.
 template <bool kCount>
-__device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const float4* lds_nodes,
-                                         int32_t n_lds, const TriRec* __restrict__ tris,
+__device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, int32_t n_lds,
+                                         const TriRec* __restrict__ tris,
                                          int32_t n_tris, LaneStack st, f3 o, f3 d, float tmin,
                                          int32_t skip, Best& b, Counters& cnt) {
   const RayW ray = make_ray(o, d, n_tris);
@@ -613,7 +622,7 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, const
           if (e >= 0) node = e; else leaf = ~e;
         }
         if (node >= 0 && leaf < 0) {
-          if (!visit_node<kCount>(gnodes, lds_nodes, n_lds, inv, oi, b.t, st, node, leaf, cnt)) {
+          if (!visit_node<kCount>(gnodes, n_lds, inv, oi, b.t, st, node, leaf, cnt)) {
             ok = false;
             node = -1;
             leaf = -1;
@@ -943,19 +952,20 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   constexpr bool kGradAcc = kGrad || kMode == kBackward;
   constexpr bool kFwd = kMode != kBackward;
   constexpr bool kTally = kMode == kForwardTally;
-  // Block tallies sit at the start of LDS: the hit map first (a constant
-  // base, so no register holds its address through the loop; per cell an
-  // int32 hit count, or with gradients 4 FP64 scores followed by the hit
-  // count, 40 bytes), then the loss table and the arrival-time histogram at
-  // the byte offsets the host chose (negative: that table goes straight to
-  // device memory).
+  // LDS: the staged BVH levels from address 0 (the node fetch relies on it),
+  // the traversal-stack windows, the counting mode's counters, then the block
+  // tallies: the hit map first (per cell an int32 hit count, or with
+  // gradients 4 FP64 scores followed by the hit count, 40 bytes), then the
+  // loss table and the arrival-time histogram at the byte offsets the host
+  // chose within the tallies (negative: that table goes straight to device
+  // memory).
   constexpr int32_t kTallyStride = kGrad ? 40 : 4;
   constexpr int32_t kTallyHitOffset = kGrad ? 32 : 0;
-  char* const tally = reinterpret_cast<char*>(lds);
-  float4* lds_nodes = kTally ? lds + a.tally_bytes / 16 : lds;
+  float4* lds_nodes = lds;
   int32_t* stack_base = reinterpret_cast<int32_t*>(lds_nodes + a.n_lds_nodes * 8);
   unsigned long long* blk_stats =
       reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
+  char* const tally = reinterpret_cast<char*>(blk_stats + kStatsWords);
   const float4* gn = reinterpret_cast<const float4*>(a.nodes);
   for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
   if (kCount)
@@ -967,7 +977,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   lds_i32* const stack_bottom = (lds_i32*)(stack_base) +
                                 (threadIdx.x >> 6) * (a.stack_lds * 64) + (threadIdx.x & 63);
-  LaneStack stack{stack_bottom, stack_bottom, 64 * (a.stack_lds - 4), a.stack_overflow + gtid,
+  LaneStack stack{stack_bottom, stack_bottom, 256 * (a.stack_lds - 4), a.stack_overflow + gtid,
                   int64_t(gridDim.x) * blockDim.x, a.stack_total, 0};
   const uint32_t lane = lane_rank(~0ull);
   const uint32_t batch_trigger = 64u - uint32_t(a.wave_batch);  // run the phase at <= this
@@ -1188,8 +1198,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         if (e >= 0) node = e; else leaf = ~e;
       }
       if (node >= 0) {
-        if (!visit_node<kCount>(a.nodes, lds_nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf,
-                                cnt)) {
+        if (!visit_node<kCount>(a.nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf, cnt)) {
           b.tri = kTraversalFailed;
           state = kWaiting;
         }
