@@ -203,8 +203,10 @@ typedef struct xp_bvh_stats {
 
 /* Build the BVH on the host (binned SAH, collapsed to 4-wide nodes) and upload
  * it.  opts may be NULL (defaults).  Must follow xp_load_mesh
- * (else XP_ERR_STATE).  Meshes of 2^28 or more triangles are rejected
- * (XP_ERR_UNSUPPORTED: leaf ranges are packed into 31 bits).  Synchronizes the
+ * (else XP_ERR_STATE).  Meshes of 2^24 or more triangles are rejected
+ * (XP_ERR_UNSUPPORTED: the kernels address the triangle records by 32-bit
+ * byte offsets), and reference splitting stops below 2^24 references.
+ * Synchronizes the
  * device.  Errors: XP_ERR_STATE, XP_ERR_INVALID_ARG, XP_ERR_MESH, XP_ERR_OOM,
  * XP_ERR_HIP, XP_ERR_UNSUPPORTED. */
 int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts);

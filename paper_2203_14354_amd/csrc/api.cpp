@@ -657,8 +657,8 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   double split_budget = 0.0;
   const int oc = parse_bvh_options(ctx, opts, leaf, bins, split_budget);
   if (oc != XP_OK) return oc;
-  if (int64_t(ctx->mat_in.size()) >= (int64_t(1) << 28))
-    return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
+  if (int64_t(ctx->mat_in.size()) >= xp::kMaxReferences)
+    return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses fewer than 2^24 triangles");
   if (ctx->channel_set && int32_t(ctx->channel.size()) <= ctx->max_sensor)
     return fail(ctx, XP_ERR_STATE, "channel map does not cover the mesh's sensor ids");
   try {
@@ -722,14 +722,14 @@ int xp_bvh_build_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t 
                       int64_t nodes_capacity, void* records, int64_t records_capacity) {
   if (!vtx || !tri || !info) return fail(nullptr, XP_ERR_INVALID_ARG, "null argument");
   try {
+    if (nt >= xp::kMaxReferences)
+      return fail(nullptr, XP_ERR_UNSUPPORTED, "the BVH addresses fewer than 2^24 triangles");
     int rc = check_geometry(nullptr, vtx, nv, tri, nt);
     if (rc != XP_OK) return rc;
     int leaf = 1, bins = 32;
     double split_budget = 0.0;
     rc = parse_bvh_options(nullptr, opts, leaf, bins, split_budget);
     if (rc != XP_OK) return rc;
-    if (nt >= (int64_t(1) << 28))
-      return fail(nullptr, XP_ERR_UNSUPPORTED, "the BVH addresses at most 2^28 triangles");
     const auto t0 = std::chrono::steady_clock::now();
     const std::vector<int32_t> zero(size_t(nt), 0), none(size_t(nt), -1);
     xp::BvhResult r;

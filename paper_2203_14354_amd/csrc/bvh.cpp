@@ -183,8 +183,8 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
     err = "empty mesh";
     return false;
   }
-  if (nt >= kMaxLeafFirst) {
-    err = "mesh has 2^28 or more triangles";
+  if (nt >= kMaxReferences) {
+    err = "mesh has 2^24 or more triangles";
     return false;
   }
   if (max_leaf < 1 || max_leaf > 8) {
@@ -195,7 +195,7 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
   std::vector<Box> tb;
   std::vector<int32_t> ref_tri;
   const int64_t budget = std::min<int64_t>(int64_t(split_budget * double(nt)),
-                                           int64_t(kMaxLeafFirst) - 1 - nt);
+                                           kMaxReferences - 1 - nt);
   {
     std::priority_queue<Piece> heap;
     std::vector<Piece> done;
@@ -279,7 +279,7 @@ bool build_bvh4(const float* vtx, const int32_t* tri, int64_t nt, const int32_t*
     }
   }
   const int64_t nr = int64_t(tb.size());
-  if (nr >= kMaxLeafFirst) {
+  if (nr >= kMaxReferences) {
     err = "too many triangle references";
     return false;
   }

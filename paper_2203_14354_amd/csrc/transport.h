@@ -359,7 +359,7 @@ __device__ __forceinline__ bool model_reflection(Photon& p, f3 nhat, float n1, c
 struct RayW {
   f3 o;           // rotated origin
   float sx, sy, sz;
-  int32_t toff;   // record offset of the rotated triangle copy
+  uint32_t toff;  // byte offset of the rotated triangle copy (records are 48 bytes)
 };
 
 __device__ __forceinline__ RayW make_ray(f3 o, f3 d, int32_t n_tris) {
@@ -373,7 +373,7 @@ __device__ __forceinline__ RayW make_ray(f3 o, f3 d, int32_t n_tris) {
   r.sx = hw_div(comp(d, kx), dz);
   r.sy = hw_div(comp(d, ky), dz);
   r.sz = hw_rcp(dz);
-  r.toff = kx * n_tris;  // (kz + 1) mod 3 == kx
+  r.toff = uint32_t(kx) * uint32_t(n_tris) * 48u;  // (kz + 1) mod 3 == kx
   return r;
 }
 
@@ -410,20 +410,29 @@ struct Best {
   int32_t rec;   // record index
 };
 
+// Records are addressed by 32-bit byte offsets from the array start (fewer
+// than 2^24 references per copy, so record index x 48 fits a 24-bit multiply
+// and the three copies fit 4 GB).
 __device__ __forceinline__ void test_triangle(const TriRec* __restrict__ tris, int32_t k,
                                               const RayW& r, float tmin, int32_t skip, Best& b) {
-  const TriRec& rec = tris[r.toff + k];  // the copy rotated for this ray
-  const float4 A = *reinterpret_cast<const float4*>(rec.a);
-  const float4 B = *reinterpret_cast<const float4*>(rec.b);
-  const float4 C = *reinterpret_cast<const float4*>(rec.c);
+  const char* base = reinterpret_cast<const char*>(tris);
+  const uint32_t off = __umul24(uint32_t(k), 48u) + r.toff;  // the copy rotated for this ray
+  const float4 A = *reinterpret_cast<const float4*>(base + off);
+  const float4 B = *reinterpret_cast<const float4*>(base + off + 16u);
+  const float4 C = *reinterpret_cast<const float4*>(base + off + 32u);
   const int32_t id = __float_as_int(A.w);
   const float va[3] = {A.x, A.y, A.z}, vb[3] = {B.x, B.y, B.z}, vc[3] = {C.x, C.y, C.z};
   const float t = intersect(r, va, vb, vc);
-  // the skipped triangle is rejected only here (an early return on its id
-  // lets the compiler load the id alone first, a second memory round trip);
-  // selects instead of branches: ties in t go to the lower triangle index
-  const bool hit = (id != skip) & (t > tmin) & (t <= b.t) & (t < kInfF);
-  const bool take = hit & ((t < b.t) | (b.tri < 0) | (id < b.tri));
+  // The closest hit orders by (distance, triangle index): for distances >= 0
+  // the float bits order as the values do, so the pair is one 64-bit key, and
+  // "nearer, or as near with a lower index" is one unsigned comparison.  No
+  // hit yet has index -1 (all ones), so any hit at the search bound itself
+  // is taken.  The skipped triangle is rejected only here (an early return on
+  // its id lets the compiler load the id alone first, a second memory round
+  // trip); selects instead of branches.
+  const uint64_t key = (uint64_t(__float_as_uint(t)) << 32) | uint32_t(id);
+  const uint64_t best = (uint64_t(__float_as_uint(b.t)) << 32) | uint32_t(b.tri);
+  const bool take = (id != skip) & (t > tmin) & (t < kInfF) & (key < best);
   b.t = take ? t : b.t;
   b.tri = take ? id : b.tri;
   b.rec = take ? k : b.rec;

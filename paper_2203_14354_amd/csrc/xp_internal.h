@@ -40,6 +40,9 @@ struct alignas(128) Node4 {
 };
 constexpr int32_t kEmptyChild = -1 - 0x7fffffff;
 constexpr int64_t kMaxLeafFirst = int64_t(1) << 28;  // leaf ranges pack first << 3
+// triangle references (triangles plus split pieces): the kernels address the
+// three record copies by 32-bit byte offsets with a 24-bit multiply
+constexpr int64_t kMaxReferences = int64_t(1) << 24;
 static_assert(sizeof(Node4) == 128, "Node4 must be one 128-byte line");
 
 // Triangle record in leaf order, three 16-byte vectors:

@@ -317,3 +317,16 @@ def test_split_depth_limit():
     info2, _, _ = R.bvh_build_host(v2, t2, split_budget=4.0)
     assert info2["n_references"] <= 2 + 8
     assert info2["max_stack"] >= info2["depth"]
+
+
+def test_meshes_of_2_24_triangles_are_rejected():
+    """The kernels address the three triangle-record copies by 32-bit byte
+    offsets (record index x 48 by a 24-bit multiply), so the builder refuses
+    2^24 triangles and stops reference splitting below 2^24 references."""
+    v = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]], np.float32)
+    t = np.zeros((1 << 24, 3), np.int32)
+    t[:, 1], t[:, 2] = 1, 2
+    with pytest.raises(_lib.XpError, match="2\\^24"):
+        R.bvh_build_host(v, t)
+    info, _, _ = R.bvh_build_host(v, t[:1000], split_budget=4.0)
+    assert info["n_references"] < 1 << 24
