@@ -234,7 +234,7 @@ __global__ void sample_kernel(int32_t kind, uint32_t s0, uint32_t s1, uint64_t p
   } else if (kind == 2) {
     p.dir = f3{in_dir[3 * i], in_dir[3 * i + 1], in_dir[3 * i + 2]};
     p.pol = f3{in_pol[3 * i], in_pol[3 * i + 1], in_pol[3 * i + 2]};
-    rayleigh(p, s0, s1, pid, 1u);
+    rayleigh(p, s0, s1, pid, 1u, draw(s0, s1, pid, 1u, 2u));
   } else {
     p.dir = cylinder_point(s0, s1, pid, cyl_r, zlo, zhi);  // the transport's emission code
   }

@@ -163,16 +163,17 @@ enum : int32_t {
 };
 
 // dipole Rayleigh scattering: isotropic trial k', keep with probability
-// 1 - (e.k')^2; new polarization = e projected off k' (trial 64 kept if all fail)
+// 1 - (e.k')^2; new polarization = e projected off k' (trial 64 kept if all
+// fail).  Trial j uses Philox block (step, 2 + j); r is trial 0's block.
 __device__ __forceinline__ void rayleigh(Photon& p, uint32_t s0, uint32_t s1, uint64_t pid,
-                                         uint32_t step) {
-  f3 k{0.f, 0.f, 1.f}, e{1.f, 0.f, 0.f};
-  for (uint32_t j = 0; j < 64; ++j) {
-    const R4 r = draw(s0, s1, pid, step, 2u + j);
+                                         uint32_t step, R4 r) {
+  f3 k, e;
+  for (uint32_t j = 0;;) {
     k = isotropic(r.u0, r.u1);
     const float ek = dot(p.pol, k);
     e = p.pol - ek * k;
-    if (r.u2 < 1.0f - ek * ek) break;
+    if (r.u2 < 1.0f - ek * ek || ++j == 64u) break;
+    r = draw(s0, s1, pid, step, 2u + j);
   }
   p.dir = k;
   p.pol = normalize(e);
@@ -789,6 +790,10 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
   }
   const int32_t step = p.steps;
   const DevMaterial m = material_at(a, p.medium, p.wavelength);
+  // the interaction's first random block, drawn for every lane at once: the
+  // Lambertian block (sub 1) of a surface event, Rayleigh trial 0 (sub 2) of
+  // a bulk event (one Philox pass instead of one per kind of interaction)
+  const R4 r1 = draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), b.tri < 0 ? 2u : 1u);
   const float d_abs = sd.d_abs, d_sca = sd.d_sca;
   const float d_bulk = fminf(d_abs, d_sca);
   const bool in_grad = p.medium == a.grad_material;
@@ -805,7 +810,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
       return true;
     }
     if (kGradAcc && in_grad) p.n_sca += 1;
-    rayleigh(p, a.seed_lo, a.seed_hi, pid, uint32_t(step));
+    rayleigh(p, a.seed_lo, a.seed_hi, pid, uint32_t(step), r1);
     p.last_tri = -1;
   } else {
     const int32_t k = b.tri;
@@ -872,7 +877,7 @@ __device__ __forceinline__ bool finish_step(Photon& p, const LaunchArgs& a, uint
       } else {
         bool through = false;
         if (u < s.c_diffuse) {
-          lambertian(p, n_back, draw(a.seed_lo, a.seed_hi, pid, uint32_t(step), 1u));
+          lambertian(p, n_back, r1);
           if (kGradAcc && gpar == 2) p.sum_inv_r += s.inv_r;
         } else if (u < s.c_specular) {
           specular(p, N);
