@@ -349,6 +349,7 @@ void choose_block_tally(const xp_context* ctx, const xp_sources* src, const xp_l
     }
   }
   if (bytes == 0) return;
+  bytes = (bytes + 127) & ~size_t(127);  // the staged nodes after them stay 128-byte aligned
   auto fits = [&](int32_t n_nodes) {
     const size_t lds = xp::propagate_lds_bytes(n_nodes, a.stack_lds, cfg.block_size, bytes);
     int per_cu = 0;

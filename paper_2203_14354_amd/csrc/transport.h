@@ -445,20 +445,23 @@ struct Counters {
 };
 
 // Node fetch: the first n_lds nodes (the top levels, breadth-first) are read
-// from LDS, where they start at address 0, the rest from global memory.  The
-// box planes are fetched in the order the ray meets them (near before far on
-// each axis, by the signs of its direction), so the slab test needs no
-// per-axis min / max: with a non-negative reciprocal the lower plane's entry
-// distance is the smaller one (rounding is monotone), and the reciprocals are
-// never zero.  Both paths read the node at the same byte offsets: a node is
+// from LDS, where they start at byte address lds_base (a multiple of 128:
+// 0, or the size of the block tallies before them), the rest from global
+// memory.  The box planes are fetched in the order the ray meets them (near
+// before far on each axis, by the signs of its direction), so the slab test
+// needs no per-axis min / max: with a non-negative reciprocal the lower
+// plane's entry distance is the smaller one (rounding is monotone), and the
+// reciprocals are never zero.  Both paths read the node at the same byte
+// offsets, the global path from a base moved back by lds_base: a node is
 // 128 bytes, each axis's lower and upper planes 16 bytes apart in a 32-byte
-// pair, so the near plane is at (node << 7) | 16 * sign and the far plane at
-// that offset ^ 16.
+// pair, so the near plane is at (node << 7) + lds_base | 16 * sign and the
+// far plane at that offset ^ 16.
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const f4v lds_f4;
 __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, int32_t n_lds,
-                                           int32_t node, f3 inv, float4 (&q)[7]) {
-  const uint32_t base = uint32_t(node) << 7;
+                                           uint32_t lds_base, int32_t node, f3 inv,
+                                           float4 (&q)[7]) {
+  const uint32_t base = (uint32_t(node) << 7) + lds_base;
   const uint32_t xn = base | ((__float_as_uint(inv.x) >> 31) << 4);
   const uint32_t yn = base | ((__float_as_uint(inv.y) >> 31) << 4);
   const uint32_t zn = base | ((__float_as_uint(inv.z) >> 31) << 4);
@@ -472,7 +475,7 @@ __device__ __forceinline__ void fetch_node(const Node4* __restrict__ gnodes, int
       q[i] = make_float4(v.x, v.y, v.z, v.w);
     }
   } else {
-    const char* g = reinterpret_cast<const char*>(gnodes);
+    const char* g = reinterpret_cast<const char*>(gnodes) - lds_base;
 #pragma unroll
     for (int i = 0; i < 7; ++i) q[i] = *reinterpret_cast<const float4*>(g + off[i]);
   }
@@ -531,11 +534,11 @@ struct LaneStack {
 // (first << 3 | count - 1).  Returns false if the stack bound is exceeded.
 template <bool kCount>
 __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes, int32_t n_lds,
-                                           f3 inv, f3 oi,
+                                           uint32_t lds_base, f3 inv, f3 oi,
                                            float tmax, LaneStack& st, int32_t& node,
                                            int32_t& leaf, Counters& cnt) {
   float4 q[7];
-  fetch_node(gnodes, n_lds, node, inv, q);
+  fetch_node(gnodes, n_lds, lds_base, node, inv, q);
   if (kCount) cnt.nodes++;
   const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};  // near planes
   const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};  // far planes
@@ -632,7 +635,7 @@ __device__ __forceinline__ bool traverse(const Node4* __restrict__ gnodes, int32
           if (e >= 0) node = e; else leaf = ~e;
         }
         if (node >= 0 && leaf < 0) {
-          if (!visit_node<kCount>(gnodes, n_lds, inv, oi, b.t, st, node, leaf, cnt)) {
+          if (!visit_node<kCount>(gnodes, n_lds, 0u, inv, oi, b.t, st, node, leaf, cnt)) {
             ok = false;
             node = -1;
             leaf = -1;
@@ -966,20 +969,22 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   constexpr bool kGradAcc = kGrad || kMode == kBackward;
   constexpr bool kFwd = kMode != kBackward;
   constexpr bool kTally = kMode == kForwardTally;
-  // LDS: the staged BVH levels from address 0 (the node fetch relies on it),
-  // the traversal-stack windows, the counting mode's counters, then the block
-  // tallies: the hit map first (per cell an int32 hit count, or with
-  // gradients 4 FP64 scores followed by the hit count, 40 bytes), then the
-  // loss table and the arrival-time histogram at the byte offsets the host
-  // chose within the tallies (negative: that table goes straight to device
-  // memory).
+  // LDS: the block tallies (kForwardTally launches) from address 0, a
+  // constant base, so no register holds their address through the loop: the
+  // hit map first (per cell an int32 hit count, or with gradients 4 FP64
+  // scores followed by the hit count, 40 bytes), then the loss table and the
+  // arrival-time histogram at the byte offsets the host chose (negative: that
+  // table goes straight to device memory); the staged BVH levels from
+  // node_lds (the tallies' size, a multiple of 128; 0 without tallies), the
+  // traversal-stack windows and the counting mode's counters.
   constexpr int32_t kTallyStride = kGrad ? 40 : 4;
   constexpr int32_t kTallyHitOffset = kGrad ? 32 : 0;
-  float4* lds_nodes = lds;
+  char* const tally = reinterpret_cast<char*>(lds);
+  const uint32_t node_lds = kTally ? uint32_t(a.tally_bytes) : 0u;
+  float4* lds_nodes = lds + node_lds / 16;
   int32_t* stack_base = reinterpret_cast<int32_t*>(lds_nodes + a.n_lds_nodes * 8);
   unsigned long long* blk_stats =
       reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
-  char* const tally = reinterpret_cast<char*>(blk_stats + kStatsWords);
   const float4* gn = reinterpret_cast<const float4*>(a.nodes);
   for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
   if (kCount)
@@ -1212,7 +1217,8 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         if (e >= 0) node = e; else leaf = ~e;
       }
       if (node >= 0) {
-        if (!visit_node<kCount>(a.nodes, a.n_lds_nodes, inv, oi, b.t, stack, node, leaf, cnt)) {
+        if (!visit_node<kCount>(a.nodes, a.n_lds_nodes, node_lds, inv, oi, b.t, stack, node, leaf,
+                                cnt)) {
           b.tri = kTraversalFailed;
           state = kWaiting;
         }

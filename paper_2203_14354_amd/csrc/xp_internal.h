@@ -140,7 +140,7 @@ struct LaunchArgs {
   DevDispersion disp[kMaxMaterials];
   // per-workgroup LDS tallies (kForwardTally launches)
   int32_t tally_cells;     // hit-map (and gradient) cells summed in LDS, 0: device memory
-  int32_t tally_bytes;     // LDS bytes of all block tallies (a multiple of 16)
+  int32_t tally_bytes;     // LDS bytes of all block tallies (a multiple of 128)
   int32_t lds_time_off;    // byte offset of the time histogram in LDS, < 0: device memory
   int32_t lds_loss_off;    // byte offset of the loss table in LDS, < 0: device memory
   int32_t n_time_cells;    // events * time bins
