@@ -304,6 +304,32 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
   return XP_OK;
 }
 
+// Per-wave event caches of a forward launch with per-event hit maps, prefix
+// offsets and at most 64 channels, whose map is too large for the LDS block
+// tally: each wave sums the hit-map rows of its two most recent events in LDS
+// and adds them to device memory when it moves on, instead of one
+// device-memory atomic per detected photon.  Only where the extra LDS costs
+// no occupancy.  The first 80 % of the photon ids then go out in chunks of
+// kBigChunk ids (a wave meets many photons of one event), the rest in the
+// launch's chunks (an even end).
+void choose_event_cache(const xp_context* ctx, const xp_launch_cfg& cfg, bool records_or_stats,
+                        xp::LaunchArgs& a) {
+  a.event_cache = 0;
+  a.n_big_chunks = 0;
+  if (!(a.src_kind == XP_SRC_POINTS && a.offsets && a.per_source_events && a.hit_map) ||
+      records_or_stats || a.tally_bytes > 0 || ctx->n_channels > 64)
+    return;
+  const size_t lds = xp::propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, cfg.block_size, 0) +
+                     xp::event_cache_lds_bytes(cfg.block_size);
+  int per_cu = 0;
+  if (lds > ctx->max_lds ||
+      xp::max_blocks_per_cu(cfg.block_size, lds, false, false, &per_cu) != hipSuccess ||
+      per_cu < cfg.blocks_per_cu)
+    return;
+  a.event_cache = 1;
+  a.n_big_chunks = int64_t(0.8 * double(a.n_photons)) / xp::kBigChunk;
+}
+
 // Choose the per-workgroup LDS tallies of a forward launch: they remove the
 // atomic contention of tables whose few cells are hit by photons from every
 // workgroup at once: small hit maps (every detection of a short-path
@@ -840,6 +866,7 @@ int propagate_forward(xp_context* ctx, const xp_sources* src, const xp_run_param
     }
     choose_block_tally(ctx, src, cfg, d_hit_map != nullptr, d_grad != nullptr, d_records != nullptr,
                        d_stats != nullptr, a);
+    choose_event_cache(ctx, cfg, d_records != nullptr || d_stats != nullptr, a);
     return launch(ctx, a, xp::kForward, d_grad != nullptr, d_records != nullptr, d_stats != nullptr,
                   cfg, grid, static_cast<hipStream_t>(stream), fixed_counter);
   } catch (...) {

@@ -266,7 +266,8 @@ hipError_t launch_propagate(const LaunchArgs& a, int mode, bool grad, bool recor
   // block tallies only in the plain forward launch (no records, no counters)
   const bool tally = mode == kForward && a.tally_bytes > 0 && !records && !count;
   const size_t lds = propagate_lds_bytes(a.n_lds_nodes, a.stack_lds, block,
-                                         tally ? size_t(a.tally_bytes) : 0);
+                                         tally ? size_t(a.tally_bytes) : 0) +
+                     (a.event_cache ? event_cache_lds_bytes(block) : 0);
   // sources with prefix offsets: the variants with the wave-uniform source
   // cursor (records and counters keep the per-photon search; same results)
   const bool offs = a.src_kind == XP_SRC_POINTS && a.offsets != nullptr;

@@ -995,6 +995,10 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   int32_t* stack_base = reinterpret_cast<int32_t*>(lds_nodes + a.n_lds_nodes * 8);
   unsigned long long* blk_stats =
       reinterpret_cast<unsigned long long*>(stack_base + a.stack_lds * blockDim.x);
+  // event caches (offsets variants): this wave's rows after the counters
+  constexpr bool kEventCache = kOffsets && kFwd && !kTally;
+  int32_t* const ecache = reinterpret_cast<int32_t*>(blk_stats + kStatsWords) +
+                          (threadIdx.x >> 6) * (kEventCacheSlots * 64);
   const float4* gn = reinterpret_cast<const float4*>(a.nodes);
   for (int32_t i = threadIdx.x; i < a.n_lds_nodes * 8; i += blockDim.x) lds_nodes[i] = gn[i];
   if (kCount)
@@ -1020,6 +1024,15 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
   // photon of the source after it (the largest int64 if there is none)
   int64_t cur_src = 0, cur_next = 0;
   bool exhausted = false;
+  // event cache: the events of the two rows (-1: none), which row was
+  // assigned last, and whether the launch's big chunks are used up
+  int64_t erow0 = -1, erow1 = -1;
+  int32_t elast = 1;
+  bool big_done = false;
+  if (kEventCache && a.event_cache) {
+    ecache[threadIdx.x & 63] = 0;
+    ecache[64 + (threadIdx.x & 63)] = 0;
+  }
   Counters cnt{0u, 0u, 0u, 0u};
   uint32_t n_steps = 0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1073,6 +1086,12 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
 #pragma unroll
                   for (int q = 0; q < 4; ++q) atomicAdd(reinterpret_cast<double*>(t) + q, sc[q]);
                 }
+              } else if (kEventCache && a.event_cache) {
+                // the event's row in this wave's LDS cache, or device memory
+                const int32_t ch = int32_t(cell - int64_t(p.event) * a.n_channels);
+                if (p.event == erow0) atomicAdd(ecache + ch, 1);
+                else if (p.event == erow1) atomicAdd(ecache + 64 + ch, 1);
+                else atomicAdd(a.hit_map + cell, 1);
               } else if (a.hit_map) {
                 atomicAdd(a.hit_map + cell, 1);
               }
@@ -1135,18 +1154,60 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
       if (__popcll(dead) < kRefillMin) dead = 0ull;
       while (dead != 0ull && !exhausted) {
         if (pool_next >= pool_end) {
-          uint64_t base = 0;
-          if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
-          base = bcast64(base);
-          if (base >= uint64_t(a.n_photons)) {
-            exhausted = true;
-            break;
+          uint64_t base = 0, end = 0;
+          bool got = false;
+          if (kEventCache && a.event_cache) {
+            // chunks of kBigChunk ids first (work counter's low half), then
+            // the launch's chunks after them (its high half)
+            if (!big_done) {
+              uint64_t c = 0;
+              if (lane == 0) c = atomicAdd(a.work_counter, 1ull);
+              c = bcast64(c) & 0xffffffffull;
+              if (c < uint64_t(a.n_big_chunks)) {
+                base = c * uint64_t(kBigChunk);
+                end = base + uint64_t(kBigChunk);
+                got = true;
+              } else {
+                big_done = true;
+              }
+            }
+            if (!got) {
+              uint64_t c = 0;
+              if (lane == 0) c = atomicAdd(a.work_counter, 1ull << 32);
+              c = bcast64(c) >> 32;
+              base = uint64_t(a.n_big_chunks) * uint64_t(kBigChunk) + c * uint64_t(a.chunk);
+            }
+          } else {
+            if (lane == 0) base = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
+            base = bcast64(base);
+          }
+          if (!got) {
+            if (base >= uint64_t(a.n_photons)) {
+              exhausted = true;
+              break;
+            }
+            end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
           }
           pool_next = base;
-          pool_end = min(base + uint64_t(a.chunk), uint64_t(a.n_photons));
+          pool_end = end;
           if (kOffsets) {
             cur_src = wave_source_of(a, int64_t(base), lane);
             cur_next = cur_src + 1 < a.n_sources ? uniform64(a.offsets[cur_src + 1]) : INT64_MAX;
+            if (kEventCache && a.event_cache && cur_src != erow0 && cur_src != erow1) {
+              // the chunk's first event takes the row assigned longer ago: its
+              // sums go to device memory (photons of that event still in
+              // flight add there directly)
+              const int32_t r = 1 - elast;
+              const int64_t old = r == 0 ? erow0 : erow1;
+              int32_t* row = ecache + r * 64;
+              if (old >= 0 && int32_t(lane) < a.n_channels) {
+                const int32_t v = row[lane];
+                if (v != 0) atomicAdd(a.hit_map + old * a.n_channels + lane, v);
+              }
+              row[lane] = 0;
+              if (r == 0) erow0 = cur_src; else erow1 = cur_src;
+              elast = r;
+            }
           }
         }
         const uint64_t avail = pool_end - pool_next;
@@ -1237,6 +1298,13 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
       if (state == kTraversing && leaf < 0 && node < 0 && stack.sp == 0) state = kWaiting;
     }
     if (kCount) cyc_search += clock64() - t_mark;
+  }
+
+  // ---- the wave's event-cache rows to device memory ----
+  if (kEventCache && a.event_cache && int32_t(lane) < a.n_channels) {
+    const int32_t v0 = ecache[lane], v1 = ecache[64 + lane];
+    if (erow0 >= 0 && v0 != 0) atomicAdd(a.hit_map + erow0 * a.n_channels + lane, v0);
+    if (erow1 >= 0 && v1 != 0) atomicAdd(a.hit_map + erow1 * a.n_channels + lane, v1);
   }
 
   // ---- block tallies to global memory (every wave of the block has left the loop) ----

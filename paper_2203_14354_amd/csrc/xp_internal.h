@@ -18,6 +18,10 @@ constexpr int kCounterRing = 64;      // work counters of eager launches, reused
 constexpr int kGraphCounters = 256;   // work counters of launches captured in graphs
 constexpr int kStatsWords = 24;
 constexpr int kStackLds = 16;        // LDS window entries per lane
+constexpr int64_t kBigChunk = 1024;  // photon ids per chunk of an event-cache launch's first part
+constexpr int kEventCacheSlots = 2;  // events whose hit-map rows a wave sums in LDS
+// LDS of the event caches: per wave, kEventCacheSlots rows of 64 int32 counters
+inline size_t event_cache_lds_bytes(int block) { return size_t(block / 64) * kEventCacheSlots * 64 * 4; }
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
 constexpr double kDefaultSplitBudget = 0.02;  // extra BVH references from pre-splitting
@@ -107,6 +111,12 @@ struct LaunchArgs {
   int32_t per_source_events;
   int32_t chunk;
   int32_t wave_batch;      // lanes not searching before a wave runs its interaction phase
+  // per-event hit maps with prefix offsets and at most 64 channels: each wave
+  // sums the rows of its two most recent events in LDS (event_cache 1), and
+  // the first n_big_chunks chunks of kBigChunk ids go out before the rest in
+  // chunks of `chunk` ids, so that a wave sees many photons of one event
+  int32_t event_cache;
+  int64_t n_big_chunks;
   const float* dirs;
   const float* pols;
   float cyl_r, cyl_zlo, cyl_zhi;

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2203_14354_amd import workloads as W
-from tests.gpu_common import agreement, to_records
+from tests.gpu_common import agreement, hist_of_detected, to_records
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +28,27 @@ def test_batched_equals_per_event_launches(det):
         one = W.point_sources(src.positions[e:e + 1], counts=[offs[e + 1] - offs[e]])
         row = det.propagate(one, seed=4, pid_base=int(offs[e]))["hit_map"].cpu().numpy()
         assert np.array_equal(row[0], out[e])
+
+
+def test_event_cache_with_uneven_and_empty_events(det):
+    """Per-event maps with prefix offsets are summed per wave in LDS for the
+    wave's two most recent events (chunks of 1,024 ids first).  With events
+    of 0 to 20,000 photons (chunks that span many events, rows evicted while
+    photons of their events are still in flight) the map equals the
+    histogram of the records of the same launch, which adds every detection
+    to device memory directly."""
+    rng = np.random.default_rng(11)
+    n_ev = 600
+    counts = rng.choice([0, 1, 7, 100, 1500, 20000], size=n_ev, p=[.1, .1, .2, .3, .2, .1])
+    pos = W.uniform_points_in_cylinder(n_ev, W.TPC1_SRC_R, -W.TPC1_SRC_ZHALF, W.TPC1_SRC_ZHALF, 3)
+    src = W.point_sources(pos, counts=counts, per_source_events=True)
+    cached = det.propagate(src, seed=9)["hit_map"].clone()
+    out = det.propagate(src, seed=9, records=True)
+    torch.cuda.synchronize()
+    assert torch.equal(cached, out["hit_map"])
+    rec = to_records(out["records"])
+    assert np.array_equal(cached.cpu().numpy(), hist_of_detected(rec, n_ev, det.n_channels))
+    assert np.all(cached.cpu().numpy()[counts == 0] == 0)  # empty events get no hits
 
 
 def test_batched_records_match_oracle(det):
