@@ -1266,23 +1266,14 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
       t_mark = t_now;
       cnt.slots++;
     }
-    // A micro-step tests at most one triangle and then visits at most one node:
-    // when the wave's lanes are split between the two kinds of work it pays for
-    // both either way, so a lane holding a leaf and a node does both.  The
-    // closest hit does not depend on the order in which candidates are tested.
+    // A micro-step pops an entry if the lane holds nothing, visits at most one
+    // node and then tests at most one triangle (the leaf the visit's nearest
+    // hit handed over, or one popped or still held): when the wave's lanes are
+    // split between the two kinds of work it pays for both either way, so a
+    // lane that can do both does.  The closest hit does not depend on the
+    // order in which candidates are tested.
     if (state == kTraversing) {
       if (kCount) cnt.busy++;
-      if (leaf < 0 && node < 0 && stack.sp > 0) {
-        const int32_t e = stack.pop();
-        if (e >= 0) node = e; else leaf = ~e;
-      }
-      if (leaf >= 0) {
-        // one triangle per micro-step: the packed leaf advances to its next triangle
-        if (kCount) cnt.tris++;
-        test_triangle(a.tris, leaf >> 3, ray, a.eps, p.last_tri, b);
-        // next triangle of the leaf: first + 1, count - 1 (leaf + 7), or done
-        leaf = (leaf & 7) != 0 ? leaf + 7 : -1;
-      }
       if (leaf < 0 && node < 0 && stack.sp > 0) {
         const int32_t e = stack.pop();
         if (e >= 0) node = e; else leaf = ~e;
@@ -1292,7 +1283,15 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
                                 cnt)) {
           b.tri = kTraversalFailed;
           state = kWaiting;
+          node = leaf = -1;
         }
+      }
+      if (leaf >= 0) {
+        // one triangle per micro-step: the packed leaf advances to its next triangle
+        if (kCount) cnt.tris++;
+        test_triangle(a.tris, leaf >> 3, ray, a.eps, p.last_tri, b);
+        // next triangle of the leaf: first + 1, count - 1 (leaf + 7), or done
+        leaf = (leaf & 7) != 0 ? leaf + 7 : -1;
       }
       // search complete: b holds the closest hit (or none)
       if (state == kTraversing && leaf < 0 && node < 0 && stack.sp == 0) state = kWaiting;
