@@ -51,6 +51,22 @@ def test_static_entry_point_darwin(rt):
     _compare(det, ds, 200_003, 6, True)
 
 
+def test_static_entry_point_per_event_maps(rt):
+    """Per-event maps with prefix offsets take the event-cache path (chunks of
+    1,024 ids first, rows summed per wave in LDS) with the work counter in
+    the fixed scratch: the maps equal xp_propagate's, twice in a row, the
+    second launch smaller."""
+    det = rt.Detector(W.tpc1(), device=0)
+    for n_ev, seed in ((200, 11), (37, 12)):
+        ds = det.sources(W.batched_s1(n_events=n_ev).sources)
+        ref = det.propagate(ds, seed=seed)["hit_map"]
+        hm = torch.zeros_like(ref)
+        det.propagate_static(ds, hm, seed=seed)
+        torch.cuda.synchronize()
+        assert hm.shape == (n_ev, det.n_channels) and int(hm.sum()) > 0
+        assert torch.equal(hm, ref)
+
+
 def test_static_entry_point_rejects_a_launch_that_does_not_fit(rt):
     from paper_2203_14354_amd._lib import XpError
     det = rt.Detector(W.darwin(), device=0)
