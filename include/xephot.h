@@ -183,9 +183,10 @@ typedef struct xp_bvh_options {
                               piece of their area and orientation needs (long slivers,
                               fans) are clipped into pieces with tighter boxes, the most
                               wasted box area first, adding at most this fraction of the
-                              triangle count as extra references, 0..4 (0 = default 0.02;
-                              negative = no splitting).  Every piece refers to the whole
-                              triangle: results are identical either way */
+                              triangle count as extra references, 0..4 (0 = default: the
+                              larger of 0.02 and 2048 / triangles, at most 4; negative =
+                              no splitting).  Every piece refers to the whole triangle:
+                              results are identical either way */
 } xp_bvh_options;
 
 typedef struct xp_bvh_stats {

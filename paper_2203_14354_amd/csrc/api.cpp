@@ -513,14 +513,15 @@ int check_geometry(xp_context* ctx, const float* vtx, int64_t nv, const int32_t*
   return XP_OK;
 }
 
-// BVH build options with their defaults filled in.
-int parse_bvh_options(xp_context* ctx, const xp_bvh_options* opts, int& leaf, int& bins,
-                      double& split_budget) {
+// BVH build options with their defaults filled in (the split budget's
+// default depends on the triangle count nt).
+int parse_bvh_options(xp_context* ctx, const xp_bvh_options* opts, int64_t nt, int& leaf,
+                      int& bins, double& split_budget) {
   leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 1;
   bins = opts && opts->sah_bins ? opts->sah_bins : 32;
   const float sb = opts ? opts->split_budget : 0.0f;
   if (!(sb <= 4.0f)) return fail(ctx, XP_ERR_INVALID_ARG, "split_budget must be at most 4");
-  split_budget = sb == 0.0f ? xp::kDefaultSplitBudget : (sb < 0.0f ? 0.0 : double(sb));
+  split_budget = sb == 0.0f ? xp::default_split_budget(nt) : (sb < 0.0f ? 0.0 : double(sb));
   if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64)
     return fail(ctx, XP_ERR_INVALID_ARG, "max_leaf_size must be 1..8, sah_bins 4..64");
   return XP_OK;
@@ -682,7 +683,7 @@ int xp_build_bvh(xp_context* ctx, const xp_bvh_options* opts) {
   if (!ctx->mesh_loaded) return fail(ctx, XP_ERR_STATE, "xp_load_mesh has not been called");
   int leaf = 1, bins = 32;
   double split_budget = 0.0;
-  const int oc = parse_bvh_options(ctx, opts, leaf, bins, split_budget);
+  const int oc = parse_bvh_options(ctx, opts, int64_t(ctx->mat_in.size()), leaf, bins, split_budget);
   if (oc != XP_OK) return oc;
   if (int64_t(ctx->mat_in.size()) >= xp::kMaxReferences)
     return fail(ctx, XP_ERR_UNSUPPORTED, "the BVH addresses fewer than 2^24 triangles");
@@ -755,7 +756,7 @@ int xp_bvh_build_host(const float* vtx, int64_t nv, const int32_t* tri, int64_t 
     if (rc != XP_OK) return rc;
     int leaf = 1, bins = 32;
     double split_budget = 0.0;
-    rc = parse_bvh_options(nullptr, opts, leaf, bins, split_budget);
+    rc = parse_bvh_options(nullptr, opts, nt, leaf, bins, split_budget);
     if (rc != XP_OK) return rc;
     const auto t0 = std::chrono::steady_clock::now();
     const std::vector<int32_t> zero(size_t(nt), 0), none(size_t(nt), -1);

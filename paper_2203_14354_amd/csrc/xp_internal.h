@@ -24,7 +24,18 @@ constexpr int kEventCacheSlots = 2;  // events whose hit-map rows a wave sums in
 inline size_t event_cache_lds_bytes(int block) { return size_t(block / 64) * kEventCacheSlots * 64 * 4; }
 constexpr int kWaveBatch = 32;       // lanes per wave interaction phase
 constexpr int kMaxThreadsPerCu = 2048;
-constexpr double kDefaultSplitBudget = 0.02;  // extra BVH references from pre-splitting
+// Default pre-splitting budget: extra BVH references up to 2 % of the
+// triangles, but at least 2,048 pieces (at most 4 per triangle).  A mesh of a
+// few thousand triangles stays shallow when its fan slivers are split (on a
+// 4,128-triangle TPC 0.45-0.6 extra references per triangle are fastest),
+// while on a mesh of ~5e5 triangles more than 2 % deepens the tree for little
+// gain.
+constexpr double kDefaultSplitBudget = 0.02;
+constexpr double kDefaultSplitPieces = 2048.0;
+inline double default_split_budget(int64_t n_triangles) {
+  const double b = n_triangles > 0 ? kDefaultSplitPieces / double(n_triangles) : 4.0;
+  return b < kDefaultSplitBudget ? kDefaultSplitBudget : (b > 4.0 ? 4.0 : b);
+}
 constexpr size_t kMaxTallyBytes = 16384;  // LDS per workgroup for pre-summed tallies
 constexpr size_t kMaxTimeTallyBytes = 8192;   // time histograms up to this size go to LDS
 constexpr size_t kMaxLossTallyBytes = 4096;   // loss tables up to this size go to LDS

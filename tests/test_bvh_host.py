@@ -62,6 +62,12 @@ def leaf_boxes(nodes, n_refs):
     return lo, hi, held
 
 
+def default_budget(nt):
+    """The builder's default split budget: extra references up to 2 % of the
+    triangles, at least 2,048 pieces, at most 4 per triangle."""
+    return min(4.0, max(0.02, 2048.0 / nt))
+
+
 @pytest.fixture(scope="module", params=[("fan_drum", 0.0), ("fan_drum", 1.0), ("fan_drum", -1.0),
                                         ("tpc1_plane", 0.0), ("tpc1_plane", 0.5)],
                 ids=lambda p: f"{p[0]}-split{p[1]}")
@@ -79,7 +85,7 @@ def test_sizes_and_reference_budget(built):
     assert info["n_triangles"] == nt
     assert len(built["nodes"]) == info["n_nodes"] and info["node_bytes"] == 128 * info["n_nodes"]
     assert len(built["recs"]) == 3 * n_refs and info["triangle_bytes"] == 3 * 48 * n_refs
-    budget = 0.02 if built["split"] == 0.0 else max(built["split"], 0.0)
+    budget = default_budget(nt) if built["split"] == 0.0 else max(built["split"], 0.0)
     assert nt <= n_refs <= nt + int(budget * nt) + 1
     if built["split"] < 0:
         assert n_refs == nt
@@ -289,7 +295,7 @@ def test_tiny_meshes(split):
     for v, t in (sliver, pair):
         info, nodes, recs = R.bvh_build_host(v, t, split_budget=split)
         nt, n = len(t), info["n_references"]
-        budget = 0.02 if split == 0.0 else max(split, 0.0)
+        budget = default_budget(nt) if split == 0.0 else max(split, 0.0)
         assert nt <= n <= nt + int(budget * nt)
         lo, hi, held = leaf_boxes(nodes, n)
         assert np.all(held == 1)
@@ -330,3 +336,22 @@ def test_meshes_of_2_24_triangles_are_rejected():
         R.bvh_build_host(v, t)
     info, _, _ = R.bvh_build_host(v, t[:1000], split_budget=4.0)
     assert info["n_references"] < 1 << 24
+
+
+def test_default_split_budget_scales_with_the_mesh():
+    """The default budget adds at least 2,048 pieces on a small mesh (the
+    4,256-triangle TPC with its plane: its fan wedges take them all) and 2 % of
+    the triangles on a large one; an explicit budget overrides it."""
+    v, t = MESHES["tpc1_plane"]()
+    nt = len(t)
+    info, _, _ = R.bvh_build_host(v, t)
+    assert info["n_references"] == nt + 2048
+    info, _, _ = R.bvh_build_host(v, t, split_budget=0.02)
+    assert info["n_references"] == nt + int(0.02 * nt)
+    big_v, big_t = MESHES["fan_drum"]()
+    reps = max(1, 120_000 // len(big_t))  # ~1.2e5 triangles: 2 % is more than 2,048
+    vv = np.concatenate([np.asarray(big_v, np.float32) + np.float32(3.0 * k) for k in range(reps)])
+    tt = np.concatenate([np.asarray(big_t, np.int32) + k * len(big_v) for k in range(reps)])
+    info, _, _ = R.bvh_build_host(vv, tt)
+    assert len(tt) * 0.02 > 2048
+    assert len(tt) < info["n_references"] <= len(tt) + int(0.02 * len(tt))
