@@ -578,7 +578,7 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes, int
     const bool is_nearest = j == uint32_t(i);
     near_entry = is_nearest ? child[i] : near_entry;
     st.put(npush, child[i]);
-    npush += (key[i] != ~0u) & !is_nearest ? 1 : 0;
+    npush += ((key[i] != ~0u) & !is_nearest) ? 1 : 0;
   }
   const bool any = nearest != ~0u;
   const bool near_leaf = any & (near_entry < 0);
@@ -588,7 +588,7 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes, int
     st.put(npush, ~leaf);
     ++npush;
   }
-  node = any & (near_entry >= 0) ? near_entry : -1;
+  node = (any & (near_entry >= 0)) ? near_entry : -1;
   leaf = near_leaf ? ~near_entry : leaf;
   if (st.sp + npush > st.total) return false;
   st.advance(npush);
