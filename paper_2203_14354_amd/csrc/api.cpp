@@ -309,7 +309,7 @@ int prepare(xp_context* ctx, const xp_sources* src, const xp_run_params* rp,
 // tally: each wave sums the hit-map rows of its two most recent events in LDS
 // and adds them to device memory when it moves on, instead of one
 // device-memory atomic per detected photon.  Only where the extra LDS costs
-// no occupancy.  The first 80 % of the photon ids then go out in chunks of
+// no occupancy.  The first 90 % of the photon ids then go out in chunks of
 // kBigChunk ids (a wave meets many photons of one event), the rest in the
 // launch's chunks (an even end).
 void choose_event_cache(const xp_context* ctx, const xp_launch_cfg& cfg, bool records_or_stats,
@@ -327,7 +327,7 @@ void choose_event_cache(const xp_context* ctx, const xp_launch_cfg& cfg, bool re
       per_cu < cfg.blocks_per_cu)
     return;
   a.event_cache = 1;
-  a.n_big_chunks = int64_t(0.8 * double(a.n_photons)) / xp::kBigChunk;
+  a.n_big_chunks = int64_t(0.9 * double(a.n_photons)) / xp::kBigChunk;
 }
 
 // Choose the per-workgroup LDS tallies of a forward launch: they remove the

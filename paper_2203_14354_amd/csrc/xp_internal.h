@@ -18,7 +18,7 @@ constexpr int kCounterRing = 64;      // work counters of eager launches, reused
 constexpr int kGraphCounters = 256;   // work counters of launches captured in graphs
 constexpr int kStatsWords = 24;
 constexpr int kStackLds = 16;        // LDS window entries per lane
-constexpr int64_t kBigChunk = 1024;  // photon ids per chunk of an event-cache launch's first part
+constexpr int64_t kBigChunk = 768;   // photon ids per chunk of an event-cache launch's first part
 constexpr int kEventCacheSlots = 2;  // events whose hit-map rows a wave sums in LDS
 // LDS of the event caches: per wave, kEventCacheSlots rows of 64 int32 counters
 inline size_t event_cache_lds_bytes(int block) { return size_t(block / 64) * kEventCacheSlots * 64 * 4; }

@@ -32,7 +32,7 @@ def test_batched_equals_per_event_launches(det):
 
 def test_event_cache_with_uneven_and_empty_events(det):
     """Per-event maps with prefix offsets are summed per wave in LDS for the
-    wave's two most recent events (chunks of 1,024 ids first).  With events
+    wave's two most recent events (chunks of 768 ids first).  With events
     of 0 to 20,000 photons (chunks that span many events, rows evicted while
     photons of their events are still in flight) the map equals the
     histogram of the records of the same launch, which adds every detection

@@ -53,7 +53,7 @@ def test_static_entry_point_darwin(rt):
 
 def test_static_entry_point_per_event_maps(rt):
     """Per-event maps with prefix offsets take the event-cache path (chunks of
-    1,024 ids first, rows summed per wave in LDS) with the work counter in
+    768 ids first, rows summed per wave in LDS) with the work counter in
     the fixed scratch: the maps equal xp_propagate's, twice in a row, the
     second launch smaller."""
     det = rt.Detector(W.tpc1(), device=0)
