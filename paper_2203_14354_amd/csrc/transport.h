@@ -1050,6 +1050,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
     if (kCount) t_mark = clock64();
     if (n_trav <= batch_trigger) {
       if (kCount) n_phases++;
+      __builtin_amdgcn_s_setprio(0);
       // ---- interaction of the waiting lanes ----
       bool start = false;  // lanes that begin a new step in this phase
       if (state == kWaiting) {
@@ -1259,6 +1260,11 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
         if (kCount) n_steps++;
       }
     }
+    // Search micro-steps run at a higher wave priority than interaction
+    // phases: a micro-step is a short chain of dependent loads, so when both
+    // are ready the SIMD issues the search first and lets the phases' long
+    // arithmetic fill the wait.
+    __builtin_amdgcn_s_setprio(1);
     // ---- one micro-step of every traversing lane's closest-hit search ----
     if (kCount) {
       const unsigned long long t_now = clock64();
