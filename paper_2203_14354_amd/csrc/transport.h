@@ -539,6 +539,7 @@ __device__ __forceinline__ bool visit_node(const Node4* __restrict__ gnodes, int
                                            int32_t& leaf, Counters& cnt) {
   float4 q[7];
   fetch_node(gnodes, n_lds, lds_base, node, inv, q);
+  __builtin_amdgcn_s_setprio(1);  // the node's loads are issued
   if (kCount) cnt.nodes++;
   const float lox[4] = {q[0].x, q[0].y, q[0].z, q[0].w};  // near planes
   const float hix[4] = {q[1].x, q[1].y, q[1].z, q[1].w};  // far planes
@@ -1263,8 +1264,10 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
     // Search micro-steps run at a higher wave priority than interaction
     // phases: a micro-step is a short chain of dependent loads, so when both
     // are ready the SIMD issues the search first and lets the phases' long
-    // arithmetic fill the wait.
-    __builtin_amdgcn_s_setprio(1);
+    // arithmetic fill the wait.  Within the micro-step, the code up to each
+    // group of loads (the node, the triangle record) runs at 2, the node
+    // visit's arithmetic at 1.
+    __builtin_amdgcn_s_setprio(2);
     // ---- one micro-step of every traversing lane's closest-hit search ----
     if (kCount) {
       const unsigned long long t_now = clock64();
@@ -1292,6 +1295,7 @@ __global__ void __launch_bounds__(256, 5) propagate_kernel(const LaunchArgs a) {
           node = leaf = -1;
         }
       }
+      __builtin_amdgcn_s_setprio(2);
       if (leaf >= 0) {
         // one triangle per micro-step: the packed leaf advances to its next triangle
         if (kCount) cnt.tris++;
