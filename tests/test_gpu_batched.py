@@ -51,6 +51,30 @@ def test_event_cache_with_uneven_and_empty_events(det):
     assert np.all(cached.cpu().numpy()[counts == 0] == 0)  # empty events get no hits
 
 
+@pytest.mark.parametrize("counts", [[0, 5, 1, 0, 9, 0], [0] + [100] * 7 + [0],
+                                    [0] + [95] * 9 + [0], [3, 0, 4000, 0, 2]],
+                         ids=["15-photons", "700-photons", "855-photons", "4005-photons"])
+def test_event_cache_at_the_big_chunk_boundary(det, counts):
+    """Per-event launches with no, exactly one or a few chunks of 768 ids in
+    the event-cache launch's first part (0.9 n / 768, rounded down: 0, 0, 1
+    and 4 here) and empty events at both ends: the map equals that of the
+    records launch and the histogram of its records."""
+    counts = np.asarray(counts)
+    pos = W.uniform_points_in_cylinder(len(counts), W.TPC1_SRC_R, -W.TPC1_SRC_ZHALF,
+                                       W.TPC1_SRC_ZHALF, 5)
+    src = W.point_sources(pos, counts=counts, per_source_events=True)
+    cached = det.propagate(src, seed=21)["hit_map"].clone()
+    out = det.propagate(src, seed=21, records=True)
+    torch.cuda.synchronize()
+    assert torch.equal(cached, out["hit_map"])
+    rec = to_records(out["records"])
+    assert len(rec) == counts.sum()
+    assert np.array_equal(cached.cpu().numpy(), hist_of_detected(rec, len(counts), det.n_channels))
+    assert np.all(cached.cpu().numpy()[counts == 0] == 0)
+    if counts.sum() > 100:
+        assert int(cached.sum()) > 0
+
+
 def test_batched_records_match_oracle(det):
     wl = W.batched_s1(n_events=16)
     src = wl.sources
